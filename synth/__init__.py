@@ -1,0 +1,8 @@
+"""Seeded synthetic input generators (no method arithmetic)."""
+from .generators import (V_MASK, WORKLOADS, Workload, down_events, epoch_permutations,
+                         event_cube, make_problem, model_draw, onsets, positions,
+                         reflection_events, ricker, scale_noise, streams)
+
+__all__ = ["V_MASK", "WORKLOADS", "Workload", "down_events", "epoch_permutations",
+           "event_cube", "make_problem", "model_draw", "onsets", "positions",
+           "reflection_events", "ricker", "scale_noise", "streams"]
