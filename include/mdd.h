@@ -1,0 +1,202 @@
+/*
+ * mdd.h -- C ABI of the MI355X (gfx950) stochastic multi-dimensional
+ * deconvolution library (Ravasi, Selvan and Luiken, "Stochastic
+ * Multi-Dimensional Deconvolution").
+ *
+ * The library computes, on one GPU, the stochastic gradient of the finite-sum
+ * time-domain MDD misfit over a batch of sources and the optimiser step that
+ * uses it.  Notation follows the paper's Theory section:
+ *
+ *   d  [ns][nr][nt]   down-going wavefield p+ (the kernel), float32, time
+ *   R  [nr][nvs][nt]  local reflection response (the unknown), float32, time
+ *   u  [ns][nvs][nt]  up-going wavefield p-, float32, time
+ *
+ * all C order with time fastest (traces stacked as in the vectors r_t, p-_t).
+ * The operator P+ is the multi-dimensional convolution: per frequency f the
+ * matrix product P-_f = P+_f R_f ([ns x nr] times [nr x nvs]); in time it is
+ * a circular convolution over nt samples summed over receivers.
+ *
+ * Conventions (the paper leaves them open): forward DFT exp(-2 pi i k t / nt)
+ * unnormalised, inverse with 1/nt, nfft = nt (circular, no padding), unit
+ * quadrature weights, and only the one-sided bins k < nf are kept (nf <=
+ * nt/2 + 1), which is the operator with the kernel band-limited to those
+ * bins.  The loss is reported in the time domain (Parseval: in-band residual
+ * energy plus the data's fixed out-of-band energy).
+ *
+ * Memory.  Every pointer argument is a DEVICE pointer unless its name ends in
+ * _host.  The caller allocates and owns all device memory, including the
+ * workspace; the library never allocates device memory.  A plan stores
+ * pointers into the workspace only.  Inputs passed to mdd_set_* must stay
+ * valid until that work has run on the plan's stream.
+ *
+ * Streams.  All work is enqueued asynchronously on the plan's stream (a
+ * hipStream_t passed as void*; NULL is the default stream).  One plan serves
+ * one stream and is not thread-safe.  Output scalars (loss, gradient norm)
+ * are written to device memory and are valid once the stream has reached
+ * them.
+ *
+ * Errors.  Every call validates its arguments on the host before enqueuing
+ * anything: an invalid call enqueues no work and returns a negative status.
+ * A failed HIP call returns MDD_EHIP; its hipError_t is kept by the plan
+ * (mdd_plan_last_hip_error).  Faults inside kernels surface at the next
+ * synchronising call.  Nothing is printed and no exception crosses the ABI.
+ * Batch indices must lie in [0, ns); kernels treat an index outside that
+ * range as a source whose wavefields are zero (it contributes nothing).
+ */
+#ifndef MDD_H
+#define MDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mdd_status;
+
+#define MDD_OK 0
+#define MDD_EINVAL (-1)       /* NULL pointer, unknown enum value, bad scalar */
+#define MDD_ESHAPE (-2)       /* inconsistent sizes (nf > nt/2+1, nb > nb_max, nt unsupported) */
+#define MDD_ENOMEM (-3)       /* workspace NULL, misaligned or smaller than needed */
+#define MDD_EHIP (-4)         /* a HIP runtime call failed */
+#define MDD_EUNSUPPORTED (-5) /* precision or optimiser not available */
+#define MDD_ESTATE (-6)       /* kernel / data not set before a call that needs them */
+
+/* Arithmetic of the two per-frequency complex products. */
+#define MDD_PREC_FP32 0   /* float32 MFMA, float32 accumulate */
+#define MDD_PREC_BF16X3 1 /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, float32 accumulate */
+#define MDD_PREC_FP16X3 2 /* fp16 hi+lo split with power-of-two tile scaling, float32 accumulate */
+#define MDD_PREC_BF16 3   /* single bf16 product (diagnostic: expected to miss 1e-3) */
+
+/* Plan flags. */
+#define MDD_FLAG_STORE_RF 1 /* mdd_step also writes the spectra of the updated model so the
+                               next mdd_step on the same R skips its forward transform */
+
+/* Sizes.  ns sources, nr receivers, nvs virtual sources, nt time samples
+ * (128, 256, 512 or 1024), nf retained one-sided frequency bins (1..nt/2+1),
+ * nb_max the largest batch any call on this plan will use (1..ns, <= 256). */
+typedef struct mdd_dims {
+  int32_t ns, nr, nvs, nt, nf, nb_max;
+  int32_t precision; /* MDD_PREC_* */
+  int32_t flags;     /* MDD_FLAG_* */
+} mdd_dims;
+
+/* Optimiser of mdd_step. */
+#define MDD_OPT_SGD 0   /* R <- M (R - lr g)  (Theory section: SGD iterations) */
+#define MDD_OPT_ADAM 1  /* Adam with bias correction, model kept masked */
+#define MDD_OPT_NSGD 2  /* Nesterov momentum, Sutskever form: gradient at R + mu s0;
+                           s0 <- mu s0 - lr g; R <- R + s0 */
+
+typedef struct mdd_opt {
+  int32_t kind;    /* MDD_OPT_* */
+  int32_t reserved;
+  double lr;       /* step size alpha (> 0) */
+  double beta1;    /* Adam first-moment decay, in [0, 1) */
+  double beta2;    /* Adam second-moment decay, in [0, 1) */
+  double eps;      /* Adam denominator guard (> 0) */
+  double mu;       /* Nesterov momentum, in [0, 1) */
+  int64_t t;       /* Adam: number of this step, >= 1 */
+} mdd_opt;
+
+typedef struct mdd_plan mdd_plan;
+
+/* Bytes of device workspace a plan with these sizes needs (256-byte aligned
+ * regions), or 0 if the sizes are invalid.  Pure host computation. */
+size_t mdd_workspace_bytes(const mdd_dims* dims);
+
+/* Validate dims, lay the plan out in the caller's workspace (device memory of
+ * at least mdd_workspace_bytes bytes, 256-byte aligned) and initialise its
+ * tables on `stream`.  *out receives a host-allocated plan object.
+ * Errors: EINVAL (NULL), ESHAPE (sizes), ENOMEM (workspace), EUNSUPPORTED
+ * (precision), EHIP. */
+mdd_status mdd_plan_create(const mdd_dims* dims, void* workspace, size_t ws_bytes, void* stream,
+                           mdd_plan** out);
+
+/* Release the host plan object (the workspace stays the caller's). */
+mdd_status mdd_plan_destroy(mdd_plan* plan);
+
+/* Change the stream later calls are enqueued on. */
+mdd_status mdd_plan_set_stream(mdd_plan* plan, void* stream);
+
+/* Kernel of the operator (Theory section, the down-going wavefield P+):
+ * d [ns][nr][nt] float32.  Computes and stores its spectra D_k, k < nf
+ * (layout [nf][ns][nr] complex, rows padded to 16 entries). */
+mdd_status mdd_set_kernel(mdd_plan* plan, const float* d);
+
+/* Up-going data p- (Theory section): u [ns][nvs][nt] float32.  Stores its
+ * spectra U_k, k < nf, and each source's energy outside the retained bins
+ * (float64), which the time-domain loss adds to the in-band residual energy. */
+mdd_status mdd_set_data(mdd_plan* plan, const float* u);
+
+/* Causality preconditioner C_c (Theory section): onset [nr][nvs] int32; sample
+ * t of trace (r, vs) of the gradient and of the model is kept iff
+ * t >= onset[r][vs].  NULL removes the mask. */
+mdd_status mdd_set_mask(mdd_plan* plan, const int32_t* onset);
+
+/* Forward MDC on a batch (Theory section, matrix form of the MDC integral,
+ * applied in the time domain as in Appendix A: transform, per-frequency
+ * product, inverse transform): U_out[b] = P+_{idx[b]} R, U_out [nb][nvs][nt]
+ * float32.  R [nr][nvs][nt]; idx [nb] int32 device array; 1 <= nb <= nb_max.
+ * Needs mdd_set_kernel. */
+mdd_status mdc_forward(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
+                       float* U_out);
+
+/* Adjoint MDC on a batch: G_out = sum_b P+_{idx[b]}^H V[b], G_out [nr][nvs][nt]
+ * float32, V [nb][nvs][nt].  No mask is applied.  Needs mdd_set_kernel. */
+mdd_status mdc_adjoint(mdd_plan* plan, const float* V, const int32_t* idx, int32_t nb,
+                       float* G_out);
+
+/* Mini-batch gradient of the finite-sum functional (Theory section):
+ *   loss = 1/2 sum_{b} || p-_{idx[b]} - P+_{idx[b]} R ||^2        (float64)
+ *   G    = C_c [ - sum_{b} P+_{idx[b]}^H (p-_{idx[b]} - P+_{idx[b]} R) ]
+ *   gnorm2 = || G ||^2                                              (float64)
+ * The gradient is the SUM over the batch as printed; repeated indices count
+ * twice.  G_out [nr][nvs][nt] float32; loss_out and gnorm2_out are device
+ * float64 scalars (either may be NULL).  Needs kernel and data. */
+mdd_status mdd_stoch_grad(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
+                          float* G_out, double* loss_out, double* gnorm2_out);
+
+/* One stochastic step in place: the gradient of mdd_stoch_grad at R (or, for
+ * MDD_OPT_NSGD, at R + mu s0), then the update of R and of the optimiser state
+ * s0, s1 ([nr][nvs][nt] float32 each): SGD uses neither (may be NULL), NSGD
+ * uses s0 (velocity), ADAM uses s0 (first moment) and s1 (second moment).
+ * The masked samples of R stay zero.  loss_out / gnorm2_out as above (the
+ * values at the point where the gradient was taken). */
+mdd_status mdd_step(mdd_plan* plan, float* R, float* s0, float* s1, const mdd_opt* opt,
+                    const int32_t* idx, int32_t nb, double* loss_out, double* gnorm2_out);
+
+/* Forget stored model spectra (MDD_FLAG_STORE_RF): call after changing R
+ * other than through mdd_step. */
+mdd_status mdd_invalidate_model_spectra(mdd_plan* plan);
+
+/* Largest squared singular value of the kernel at each retained frequency,
+ * lam_out [nf] device float64, by `iters` power iterations on D_k^H D_k over
+ * all ns sources (Appendix B: the operator's largest singular value is the
+ * kernel's, max over k).  Needs mdd_set_kernel. */
+mdd_status mdd_sigma_max2(mdd_plan* plan, int32_t iters, double* lam_out);
+
+/* Kernel timing with HIP events on the plan's stream.  enable != 0 starts
+ * recording (the plan keeps up to `capacity` launches, host memory);
+ * mdd_profile_read returns, per kernel class (see MDD_KC_*), the summed
+ * milliseconds and launch counts of the launches recorded so far.  It
+ * synchronises the plan's stream. */
+#define MDD_KC_FFT_MODEL 0   /* forward transform of the model */
+#define MDD_KC_GEMM 1        /* per-frequency products (+ residual, loss) */
+#define MDD_KC_UPDATE 2      /* inverse transform + mask + update (+ model transform) */
+#define MDD_KC_REDUCE 3      /* float64 reductions */
+#define MDD_KC_DATA_FFT 4    /* transforms of batch data (forward / adjoint operators) */
+#define MDD_KC_COUNT 5
+mdd_status mdd_profile_enable(mdd_plan* plan, int32_t enable, int32_t capacity);
+mdd_status mdd_profile_read(mdd_plan* plan, double* ms_host, int64_t* count_host);
+
+/* Static description of a status code. */
+const char* mdd_status_string(mdd_status status);
+
+/* The hipError_t of the last failed HIP call on this plan (0 if none). */
+int32_t mdd_plan_last_hip_error(const mdd_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDD_H */

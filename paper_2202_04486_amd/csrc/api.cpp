@@ -1,0 +1,466 @@
+// Host layer of the C ABI declared in include/mdd.h: argument validation
+// (always before any HIP call), the workspace layout, and the sequence of
+// kernel launches for each entry point on the plan's stream.
+#include <cmath>
+#include <cstdlib>
+#include <new>
+#include <vector>
+
+#include "mdd_internal.h"
+
+using namespace mdd;
+
+namespace {
+
+constexpr int MAX_EXTENT = 4096;  // ns, nr, nvs: the power iteration keeps vectors in LDS
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_nt(int nt) { return nt == 128 || nt == 256 || nt == 512 || nt == 1024; }
+
+struct Layout {
+  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, total;
+};
+
+Layout make_layout(const mdd_dims& d) {
+  const size_t nrp = round16(d.nr), nvsp = round16(d.nvs), nvb = nblocks(d.nvs);
+  const size_t c8 = sizeof(float2);
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.tw = take(c8 * d.nt);
+  L.df = take(c8 * d.nf * d.ns * nrp);
+  L.uf = take(c8 * d.nf * d.ns * nvsp);
+  L.oob = take(sizeof(double) * d.ns);
+  L.oobp = take(sizeof(double) * d.ns * nvb);
+  L.onset = take(sizeof(int32_t) * d.nr * d.nvs);
+  L.f = take(c8 * d.nr * nvb * d.nf * CB);
+  L.bsp = take(c8 * d.nb_max * nvb * d.nf * CB);
+  L.lossp = take(sizeof(double) * d.nf * nvb);
+  L.gnp = take(sizeof(double) * d.nr * nvb);
+  L.total = o;
+  return L;
+}
+
+mdd_status check_dims(const mdd_dims* d) {
+  if (!d) return MDD_EINVAL;
+  if (d->ns < 1 || d->nr < 1 || d->nvs < 1 || d->nb_max < 1 || d->nf < 1) return MDD_ESHAPE;
+  if (d->ns > MAX_EXTENT || d->nr > MAX_EXTENT || d->nvs > MAX_EXTENT) return MDD_ESHAPE;
+  if (!valid_nt(d->nt)) return MDD_ESHAPE;
+  if (d->nf > d->nt / 2 + 1) return MDD_ESHAPE;
+  if (d->nb_max > d->ns || d->nb_max > NB_LIMIT) return MDD_ESHAPE;
+  if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_BF16) return MDD_EUNSUPPORTED;
+  if (d->flags & ~MDD_FLAG_STORE_RF) return MDD_EINVAL;
+  return MDD_OK;
+}
+
+// Column groups of one frequency in the product kernels (must match launch_gemm).
+int gemm_ncg(int nb, int nvb) {
+  const int tnb = nb <= 16 ? 1 : (nb <= 32 ? 2 : 4);
+  return (nvb + tnb - 1) / tnb;
+}
+
+}  // namespace
+
+struct mdd_plan {
+  mdd_dims d{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L{};
+  int nrp = 0, nvsp = 0, nvb = 0;
+  bool kernel_set = false, data_set = false, mask_set = false;
+  // MDD_FLAG_STORE_RF: the model whose next evaluation point's spectra F holds.
+  const float* spec_model = nullptr;
+  const float* spec_vel = nullptr;
+  double spec_mu = 0.0;
+  int32_t last_hip = 0;
+  bool prof = false;
+  int cap = 0, nrec = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  float2* tw() const { return at<float2>(L.tw); }
+  float2* Df() const { return at<float2>(L.df); }
+  float2* Uf() const { return at<float2>(L.uf); }
+  double* oob() const { return at<double>(L.oob); }
+  double* oobp() const { return at<double>(L.oobp); }
+  int32_t* onset() const { return at<int32_t>(L.onset); }
+  float2* F() const { return at<float2>(L.f); }
+  float2* Bsp() const { return at<float2>(L.bsp); }
+  double* lossp() const { return at<double>(L.lossp); }
+  double* gnp() const { return at<double>(L.gnp); }
+
+  template <class Fn>
+  mdd_status run(int kclass, Fn&& fn) {
+    const bool rec = prof && nrec < cap;
+    if (rec) {
+      const hipError_t e = hipEventRecord(ev[2 * nrec], stream);
+      if (e != hipSuccess) return fail(e);
+    }
+    const hipError_t err = fn();
+    if (err != hipSuccess) return fail(err);
+    if (rec) {
+      const hipError_t e = hipEventRecord(ev[2 * nrec + 1], stream);
+      if (e != hipSuccess) return fail(e);
+      cls[nrec] = kclass;
+      ++nrec;
+    }
+    return MDD_OK;
+  }
+  mdd_status fail(hipError_t e) {
+    last_hip = (int32_t)e;
+    return MDD_EHIP;
+  }
+
+  // Trace-kernel geometry of a [rows][nvs][nt] time array against blocked spectra.
+  TraceArgs blocked(float2* spec, int rows) const {
+    TraceArgs a{};
+    a.nt = d.nt;
+    a.nf = d.nf;
+    a.rows = rows;
+    a.ncols = d.nvs;
+    a.ncb = nvb;
+    a.spec = spec;
+    a.s_row = (long long)nvb * d.nf * CB;
+    a.s_cb = (long long)d.nf * CB;
+    a.s_k = CB;
+    a.tw = tw();
+    return a;
+  }
+
+  GemmArgs gemm(const int32_t* idx, int nb) const {
+    GemmArgs g{};
+    g.Df = Df();
+    g.Uf = Uf();
+    g.F = F();
+    g.Bsp = Bsp();
+    g.idx = idx;
+    g.loss_part = lossp();
+    g.ns = d.ns;
+    g.nr = d.nr;
+    g.nrp = nrp;
+    g.nvs = d.nvs;
+    g.nvsp = nvsp;
+    g.nvb = nvb;
+    g.nf = d.nf;
+    g.nt = d.nt;
+    g.nb = nb;
+    return g;
+  }
+
+  mdd_status model_fft(const float* R, const float* vel, double mu) {
+    TraceArgs a = blocked(F(), d.nr);
+    a.x_in = R;
+    a.x_in2 = vel;
+    a.mu2 = (float)mu;
+    return run(MDD_KC_FFT_MODEL, [&] { return launch_trace(TM_RFFT, a, stream); });
+  }
+
+  mdd_status reduce(const int32_t* idx, int nb, bool with_loss, double* loss_out,
+                    double* gnorm2_out) {
+    if (!loss_out && !gnorm2_out) return MDD_OK;
+    ReduceArgs r{};
+    r.loss_part = lossp();
+    r.n_loss = with_loss ? d.nf * gemm_ncg(nb, nvb) : 0;
+    r.loss_scale = 1.0 / (2.0 * d.nt);
+    r.oob = with_loss ? oob() : nullptr;
+    r.idx = idx;
+    r.nb = nb;
+    r.ns = d.ns;
+    r.gn_part = gnp();
+    r.n_gn = d.nr * nvb;
+    r.loss_out = loss_out;
+    r.gnorm2_out = gnorm2_out;
+    return run(MDD_KC_REDUCE, [&] { return launch_reduce(r, stream); });
+  }
+};
+
+#define MDD_TRY(x)                 \
+  do {                             \
+    const mdd_status s_ = (x);     \
+    if (s_ != MDD_OK) return s_;   \
+  } while (0)
+
+extern "C" {
+
+size_t mdd_workspace_bytes(const mdd_dims* dims) {
+  if (check_dims(dims) != MDD_OK) return 0;
+  return make_layout(*dims).total;
+}
+
+mdd_status mdd_plan_create(const mdd_dims* dims, void* workspace, size_t ws_bytes, void* stream,
+                           mdd_plan** out) {
+  if (!out) return MDD_EINVAL;
+  *out = nullptr;
+  MDD_TRY(check_dims(dims));
+  const Layout L = make_layout(*dims);
+  if (!workspace || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return MDD_ENOMEM;
+  mdd_plan* p = new (std::nothrow) mdd_plan();
+  if (!p) return MDD_ENOMEM;
+  p->d = *dims;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->ws = reinterpret_cast<char*>(workspace);
+  p->L = L;
+  p->nrp = round16(dims->nr);
+  p->nvsp = round16(dims->nvs);
+  p->nvb = nblocks(dims->nvs);
+  const hipError_t e = launch_twiddles(p->tw(), dims->nt, p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return MDD_EHIP;
+  }
+  *out = p;
+  return MDD_OK;
+}
+
+mdd_status mdd_plan_destroy(mdd_plan* plan) {
+  if (!plan) return MDD_EINVAL;
+  for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+  delete plan;
+  return MDD_OK;
+}
+
+mdd_status mdd_plan_set_stream(mdd_plan* plan, void* stream) {
+  if (!plan) return MDD_EINVAL;
+  plan->stream = reinterpret_cast<hipStream_t>(stream);
+  return MDD_OK;
+}
+
+mdd_status mdd_set_kernel(mdd_plan* p, const float* d) {
+  if (!p || !d) return MDD_EINVAL;
+  TraceArgs a{};
+  a.nt = p->d.nt;
+  a.nf = p->d.nf;
+  a.rows = p->d.ns;
+  a.ncols = p->d.nr;
+  a.ncb = nblocks(p->d.nr);
+  a.x_in = d;
+  a.spec = p->Df();
+  a.s_row = p->nrp;
+  a.s_cb = CB;
+  a.s_k = (long long)p->d.ns * p->nrp;
+  a.tw = p->tw();
+  MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  p->kernel_set = true;
+  return MDD_OK;
+}
+
+mdd_status mdd_set_data(mdd_plan* p, const float* u) {
+  if (!p || !u) return MDD_EINVAL;
+  TraceArgs a{};
+  a.nt = p->d.nt;
+  a.nf = p->d.nf;
+  a.rows = p->d.ns;
+  a.ncols = p->d.nvs;
+  a.ncb = p->nvb;
+  a.x_in = u;
+  a.spec = p->Uf();
+  a.s_row = p->nvsp;
+  a.s_cb = CB;
+  a.s_k = (long long)p->d.ns * p->nvsp;
+  a.part = p->oobp();
+  a.tw = p->tw();
+  MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  MDD_TRY(p->run(MDD_KC_REDUCE, [&] {
+    return launch_row_sum(p->oobp(), p->d.ns, p->nvb, 1.0 / (2.0 * p->d.nt), p->oob(), p->stream);
+  }));
+  p->data_set = true;
+  return MDD_OK;
+}
+
+mdd_status mdd_set_mask(mdd_plan* p, const int32_t* onset) {
+  if (!p) return MDD_EINVAL;
+  if (!onset) {
+    p->mask_set = false;
+    return MDD_OK;
+  }
+  const hipError_t e = hipMemcpyAsync(p->onset(), onset, sizeof(int32_t) * p->d.nr * p->d.nvs,
+                                      hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return p->fail(e);
+  p->mask_set = true;
+  return MDD_OK;
+}
+
+mdd_status mdc_forward(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb, float* U_out) {
+  if (!p || !R || !idx || !U_out) return MDD_EINVAL;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  if (!p->kernel_set) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  MDD_TRY(p->model_fft(R, nullptr, 0.0));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FWD, p->d.precision, g, p->stream); }));
+  TraceArgs a = p->blocked(p->Bsp(), nb);
+  a.x_out = U_out;
+  return p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_IRFFT, a, p->stream); });
+}
+
+mdd_status mdc_adjoint(mdd_plan* p, const float* V, const int32_t* idx, int32_t nb, float* G_out) {
+  if (!p || !V || !idx || !G_out) return MDD_EINVAL;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  if (!p->kernel_set) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  TraceArgs a = p->blocked(p->Bsp(), nb);
+  a.x_in = V;
+  MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_ADJ, p->d.precision, g, p->stream); }));
+  TraceArgs b = p->blocked(p->F(), p->d.nr);
+  b.x_out = G_out;
+  return p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_IRFFT, b, p->stream); });
+}
+
+mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb,
+                          float* G_out, double* loss_out, double* gnorm2_out) {
+  if (!p || !R || !idx || !G_out) return MDD_EINVAL;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  MDD_TRY(p->model_fft(R, nullptr, 0.0));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, p->d.precision, g, p->stream); }));
+  TraceArgs a = p->blocked(p->F(), p->d.nr);
+  a.x_out = G_out;
+  a.onset = p->mask_set ? p->onset() : nullptr;
+  a.part = p->gnp();
+  MDD_TRY(p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_GRAD, a, p->stream); }));
+  return p->reduce(idx, nb, true, loss_out, gnorm2_out);
+}
+
+mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* opt,
+                    const int32_t* idx, int32_t nb, double* loss_out, double* gnorm2_out) {
+  if (!p || !R || !opt || !idx) return MDD_EINVAL;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
+  const mdd_opt& o = *opt;
+  if (!(o.lr > 0.0) || !std::isfinite(o.lr)) return MDD_EINVAL;
+  int mode;
+  switch (o.kind) {
+    case MDD_OPT_SGD: mode = TM_SGD; break;
+    case MDD_OPT_ADAM:
+      if (!s0 || !s1) return MDD_EINVAL;
+      if (!(o.beta1 >= 0.0 && o.beta1 < 1.0) || !(o.beta2 >= 0.0 && o.beta2 < 1.0)) return MDD_EINVAL;
+      if (!(o.eps > 0.0) || o.t < 1) return MDD_EINVAL;
+      mode = TM_ADAM;
+      break;
+    case MDD_OPT_NSGD:
+      if (!s0) return MDD_EINVAL;
+      if (!(o.mu >= 0.0 && o.mu < 1.0)) return MDD_EINVAL;
+      mode = TM_NSGD;
+      break;
+    default: return MDD_EINVAL;
+  }
+  const bool store = (p->d.flags & MDD_FLAG_STORE_RF) != 0;
+  const float* vel = mode == TM_NSGD ? s0 : nullptr;
+  const double mu = mode == TM_NSGD ? o.mu : 0.0;
+  const bool have = store && p->spec_model == R && p->spec_vel == vel && p->spec_mu == mu;
+  p->spec_model = nullptr;
+  if (!have) MDD_TRY(p->model_fft(R, vel, mu));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, p->d.precision, g, p->stream); }));
+  TraceArgs a = p->blocked(p->F(), p->d.nr);
+  a.model = R;
+  a.st0 = s0;
+  a.st1 = s1;
+  a.lr = (float)o.lr;
+  a.beta1 = (float)o.beta1;
+  a.beta2 = (float)o.beta2;
+  a.eps = (float)o.eps;
+  a.mu = (float)o.mu;
+  if (mode == TM_ADAM) {
+    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(o.beta1, (double)o.t)));
+    a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(o.beta2, (double)o.t)));
+  }
+  a.store_spec = store ? 1 : 0;
+  a.onset = p->mask_set ? p->onset() : nullptr;
+  a.part = p->gnp();
+  MDD_TRY(p->run(MDD_KC_UPDATE, [&] { return launch_trace(mode, a, p->stream); }));
+  if (store) {
+    p->spec_model = R;
+    p->spec_vel = vel;
+    p->spec_mu = mu;
+  }
+  return p->reduce(idx, nb, true, loss_out, gnorm2_out);
+}
+
+mdd_status mdd_invalidate_model_spectra(mdd_plan* p) {
+  if (!p) return MDD_EINVAL;
+  p->spec_model = nullptr;
+  return MDD_OK;
+}
+
+mdd_status mdd_sigma_max2(mdd_plan* p, int32_t iters, double* lam_out) {
+  if (!p || !lam_out) return MDD_EINVAL;
+  if (iters < 1) return MDD_EINVAL;
+  if (!p->kernel_set) return MDD_ESTATE;
+  return p->run(MDD_KC_REDUCE, [&] {
+    return launch_sigma(p->Df(), p->d.nf, p->d.ns, p->d.nr, p->nrp, iters, lam_out, p->stream);
+  });
+}
+
+mdd_status mdd_profile_enable(mdd_plan* p, int32_t enable, int32_t capacity) {
+  if (!p) return MDD_EINVAL;
+  if (!enable) {
+    p->prof = false;
+    return MDD_OK;
+  }
+  if (capacity < 1) return MDD_EINVAL;
+  if ((int)p->ev.size() < 2 * capacity) {
+    const size_t have = p->ev.size();
+    p->ev.resize(2 * (size_t)capacity, nullptr);
+    for (size_t i = have; i < p->ev.size(); ++i) {
+      const hipError_t e = hipEventCreate(&p->ev[i]);
+      if (e != hipSuccess) {
+        p->ev.resize(i);
+        return p->fail(e);
+      }
+    }
+  }
+  p->cls.assign(capacity, 0);
+  p->cap = capacity;
+  p->nrec = 0;
+  p->prof = true;
+  return MDD_OK;
+}
+
+mdd_status mdd_profile_read(mdd_plan* p, double* ms_host, int64_t* count_host) {
+  if (!p || !ms_host || !count_host) return MDD_EINVAL;
+  for (int c = 0; c < MDD_KC_COUNT; ++c) {
+    ms_host[c] = 0.0;
+    count_host[c] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->fail(e);
+  for (int i = 0; i < p->nrec; ++i) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]);
+    if (e != hipSuccess) return p->fail(e);
+    ms_host[p->cls[i]] += ms;
+    count_host[p->cls[i]] += 1;
+  }
+  p->nrec = 0;
+  return MDD_OK;
+}
+
+const char* mdd_status_string(mdd_status s) {
+  switch (s) {
+    case MDD_OK: return "ok";
+    case MDD_EINVAL: return "invalid argument";
+    case MDD_ESHAPE: return "inconsistent sizes";
+    case MDD_ENOMEM: return "workspace missing, misaligned or too small";
+    case MDD_EHIP: return "HIP runtime error";
+    case MDD_EUNSUPPORTED: return "unsupported precision or optimiser";
+    case MDD_ESTATE: return "kernel or data not set";
+    default: return "unknown status";
+  }
+}
+
+int32_t mdd_plan_last_hip_error(const mdd_plan* p) { return p ? p->last_hip : 0; }
+
+}  // extern "C"

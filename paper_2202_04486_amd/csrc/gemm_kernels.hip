@@ -1,0 +1,458 @@
+// Per-frequency complex products of the MDC operator on MFMA (Theory section,
+// matrix form P-_f = P+_f R_f; Appendix A "batched matrix-matrix
+// multiplication"), with the residual, the float64 loss partials and the
+// adjoint product fused for the mini-batch gradient:
+//
+//   Res_k = D_{b,k} R_k - U_{b,k}      ([nb x nr] [nr x nvs])
+//   G_k   = D_{b,k}^H Res_k            ([nr x nb] [nb x nvs]), written over R_k
+//
+// A workgroup owns one frequency k and a group of TNB column blocks (16
+// virtual sources each).  Its batch rows of D_k are gathered by index into
+// LDS in receiver chunks of KC, the residual block stays in LDS between the
+// two products, and R_k is read and G_k written exactly once.
+//
+// There is no complex MFMA: a complex product is four real products
+// (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br) on v_mfma_f32_16x16x4_f32, or, in
+// the split-precision forms, on v_mfma_f32_16x16x32_{bf16,f16} with each
+// operand split into hi + lo and hi*hi + hi*lo + lo*hi accumulated in fp32.
+#include "device_common.h"
+#include "mdd_internal.h"
+
+namespace mdd {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Operand of a 16x16x32 split-precision MFMA: 8 consecutive k values of one
+// row (A) or one column (B), real and imaginary parts, hi and lo.
+template <int PREC>
+struct SplitOp;
+
+template <>
+struct SplitOp<MDD_PREC_BF16X3> {
+  using V = bf16x8;
+  V rh, rl, ih, il;
+  __device__ __forceinline__ void set(int e, float2 z) {
+    const __bf16 a = (__bf16)z.x, b = (__bf16)z.y;
+    rh[e] = a;
+    ih[e] = b;
+    rl[e] = (__bf16)(z.x - (float)a);
+    il[e] = (__bf16)(z.y - (float)b);
+  }
+  static __device__ __forceinline__ floatx4 mma(V a, V b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct SplitOp<MDD_PREC_BF16> {
+  using V = bf16x8;
+  V rh, rl, ih, il;
+  __device__ __forceinline__ void set(int e, float2 z) {
+    rh[e] = (__bf16)z.x;
+    ih[e] = (__bf16)z.y;
+    rl[e] = (__bf16)0.f;
+    il[e] = (__bf16)0.f;
+  }
+  static __device__ __forceinline__ floatx4 mma(V a, V b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct SplitOp<MDD_PREC_FP16X3> {
+  using V = halfx8;
+  V rh, rl, ih, il;
+  __device__ __forceinline__ void set(int e, float2 z) {  // operands are pre-scaled
+    const _Float16 a = (_Float16)z.x, b = (_Float16)z.y;
+    rh[e] = a;
+    ih[e] = b;
+    rl[e] = (_Float16)(z.x - (float)a);
+    il[e] = (_Float16)(z.y - (float)b);
+  }
+  static __device__ __forceinline__ floatx4 mma(V a, V b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// acc += A * B (complex), or A^H-style when the caller passes conj(A).
+template <int PREC, typename Op>
+__device__ __forceinline__ void split_cmma(const Op& A, const Op& B, floatx4& re, floatx4& im) {
+  using V = typename Op::V;
+  const V nih = -A.ih, nil = -A.il;
+  if constexpr (PREC == MDD_PREC_BF16) {
+    re = Op::mma(A.rh, B.rh, re);
+    re = Op::mma(nih, B.ih, re);
+    im = Op::mma(A.rh, B.ih, im);
+    im = Op::mma(A.ih, B.rh, im);
+  } else {
+    re = Op::mma(A.rh, B.rh, re);
+    re = Op::mma(A.rh, B.rl, re);
+    re = Op::mma(A.rl, B.rh, re);
+    re = Op::mma(nih, B.ih, re);
+    re = Op::mma(nih, B.il, re);
+    re = Op::mma(nil, B.ih, re);
+    im = Op::mma(A.rh, B.ih, im);
+    im = Op::mma(A.rh, B.il, im);
+    im = Op::mma(A.rl, B.ih, im);
+    im = Op::mma(A.ih, B.rh, im);
+    im = Op::mma(A.ih, B.rl, im);
+    im = Op::mma(A.il, B.rh, im);
+  }
+}
+
+// Power-of-two scale bringing max |x| near 2^14 (fp16 split keeps 22 bits
+// for entries down to ~2^-8 of the tile maximum).
+__device__ __forceinline__ float pow2_scale(float amax) {
+  if (!(amax > 0.f) || !(amax < 3.0e38f)) return 1.f;
+  int e;
+  frexpf(amax, &e);  // amax = m 2^e, m in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
+}
+
+template <int PREC, int NBT, int TNB>
+struct GemmCfg {
+  static constexpr int MB = NBT * 16;                 // padded batch rows
+  static constexpr int NW = TNB * 16;                 // columns per workgroup
+  static constexpr int TILES = NBT * TNB;
+  static constexpr int S = TILES >= 4 ? 1 : 4 / TILES;  // waves splitting K
+  static constexpr int G = 4 / S;                     // wave groups over tiles
+  static constexpr int TPWV = TILES / G;              // tiles per wave
+  static constexpr bool SPLIT = PREC != MDD_PREC_FP32;
+  static constexpr int KSTEP = SPLIT ? 32 : 4;
+  static constexpr int KC_ = (SPLIT && S == 4) ? 128 : KC;   // receiver chunk
+  static constexpr int DST = KC_ + 2;                 // LDS row stride of D (16-byte aligned)
+  static constexpr int RST = NW + 1;                  // LDS row stride of R / residual
+  static constexpr int RS_SZ = KC_ * RST;
+  static constexpr int RED_SZ = S * MB * NW;
+  static constexpr int BUF_SZ = RS_SZ > RED_SZ ? RS_SZ : RED_SZ;
+  static constexpr int MT_ADJ = KC_ / 16;             // adjoint m-tiles per chunk
+  static constexpr int MT_PER_WAVE = MT_ADJ / 4;
+  static constexpr size_t SMEM = sizeof(float2) * ((size_t)MB * DST + BUF_SZ + (size_t)MB * RST);
+};
+
+template <int PREC, int NBT, int TNB, int KIND>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  using C = GemmCfg<PREC, NBT, TNB>;
+  constexpr int MB = C::MB, NW = C::NW, KCH = C::KC_;
+  extern __shared__ float2 smem[];
+  float2* s_d = smem;                       // [MB][DST]
+  float2* s_buf = s_d + MB * C::DST;        // R chunk [KC][RST]  |  split-K partials [S][MB][NW]
+  float2* s_res = s_buf + C::BUF_SZ;        // residual [MB][RST]
+  __shared__ int s_idx[MB];
+  __shared__ double s_red[4];
+  __shared__ float s_scale[4];              // fp16 split: D chunk, R chunk, residual scales
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+
+  // Map the linear workgroup id so that the column groups of one frequency run
+  // on the same XCD (dispatch is round-robin over the 8 XCDs): they share D_k.
+  const int ncg = (a.nvb + TNB - 1) / TNB;
+  const int total = a.nf * ncg;
+  const int bid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
+  const int k = logical / ncg, cg = logical % ncg;
+  const int blk0 = cg * TNB;
+
+  for (int b = tid; b < MB; b += 256) {
+    int s = -1;
+    if (b < a.nb) {
+      s = a.idx[b];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[b] = s;
+  }
+  __syncthreads();
+
+  auto load_d_chunk = [&](int r0) {
+    // D_{b,k}[b][r0 .. r0+KCH) -> s_d; rows b >= nb / bad index and r >= nr are zero.
+    for (int i = tid; i < MB * (KCH / 2); i += 256) {
+      const int b = i / (KCH / 2), rr = 2 * (i % (KCH / 2));
+      const int s = s_idx[b];
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (s >= 0 && r0 + rr < a.nr)
+        v = *reinterpret_cast<const float4*>(a.Df + ((size_t)k * a.ns + s) * a.nrp + r0 + rr);
+      s_d[b * C::DST + rr] = make_float2(v.x, v.y);
+      s_d[b * C::DST + rr + 1] = make_float2(v.z, v.w);
+    }
+  };
+
+  float fp16_sd = 1.f, fp16_sr = 1.f;   // used by the fp16 split form only
+  auto chunk_scale = [&](const float2* base, int rows, int stride, int cols) -> float {
+    float m = 0.f;
+    for (int i = tid; i < rows * cols; i += 256) {
+      const float2 z = base[(i / cols) * stride + (i % cols)];
+      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (lane == 0) s_scale[wave] = m;
+    __syncthreads();
+    const float amax = fmaxf(fmaxf(s_scale[0], s_scale[1]), fmaxf(s_scale[2], s_scale[3]));
+    __syncthreads();
+    return pow2_scale(amax);
+  };
+
+  // ------------------------------------------------------------ forward
+  if constexpr (KIND != GK_ADJ) {
+    floatx4 acc_re[C::TPWV], acc_im[C::TPWV];
+#pragma unroll
+    for (int t = 0; t < C::TPWV; ++t) {
+      acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int g = wave % C::G, ks = wave / C::G;
+    for (int r0 = 0; r0 < a.nr; r0 += KCH) {
+      load_d_chunk(r0);
+      float2* s_r = s_buf;
+      for (int i = tid; i < KCH * (NW / 2); i += 256) {
+        const int rr = i / (NW / 2), cc = 2 * (i % (NW / 2));
+        const int blk = blk0 + cc / 16;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r0 + rr < a.nr && blk < a.nvb)
+          v = *reinterpret_cast<const float4*>(
+              a.F + (((size_t)(r0 + rr) * a.nvb + blk) * a.nf + k) * CB + (cc & 15));
+        s_r[rr * C::RST + cc] = make_float2(v.x, v.y);
+        s_r[rr * C::RST + cc + 1] = make_float2(v.z, v.w);
+      }
+      __syncthreads();
+      floatx4 cre[C::TPWV], cim[C::TPWV];   // fp16 split: per-chunk accumulators
+      if constexpr (PREC == MDD_PREC_FP16X3) {
+        fp16_sd = chunk_scale(s_d, MB, C::DST, KCH);
+        fp16_sr = chunk_scale(s_r, KCH, C::RST, NW);
+#pragma unroll
+        for (int t = 0; t < C::TPWV; ++t) {
+          cre[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          cim[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      if constexpr (!C::SPLIT) {
+        for (int kk = ks; kk < KCH / 4; kk += C::S) {
+#pragma unroll
+          for (int t = 0; t < C::TPWV; ++t) {
+            const int tile = g + t * C::G;
+            const int mt = tile / TNB, nt = tile % TNB;
+            const float2 dv = s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq];
+            const float2 rv = s_r[(kk * 4 + lq) * C::RST + nt * 16 + lr];
+            acc_re[t] = mfma4(dv.x, rv.x, acc_re[t]);
+            acc_re[t] = mfma4(-dv.y, rv.y, acc_re[t]);
+            acc_im[t] = mfma4(dv.x, rv.y, acc_im[t]);
+            acc_im[t] = mfma4(dv.y, rv.x, acc_im[t]);
+          }
+        }
+      } else {
+        using Op = SplitOp<PREC>;
+        for (int kk = ks; kk < KCH / 32; kk += C::S) {
+#pragma unroll
+          for (int t = 0; t < C::TPWV; ++t) {
+            const int tile = g + t * C::G;
+            const int mt = tile / TNB, nt = tile % TNB;
+            Op A, B;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              float2 dv = s_d[(mt * 16 + lr) * C::DST + kk * 32 + lq * 8 + e];
+              float2 rv = s_r[(kk * 32 + lq * 8 + e) * C::RST + nt * 16 + lr];
+              if constexpr (PREC == MDD_PREC_FP16X3) {
+                dv = cscale(dv, fp16_sd);
+                rv = cscale(rv, fp16_sr);
+              }
+              A.set(e, dv);
+              B.set(e, rv);
+            }
+            if constexpr (PREC == MDD_PREC_FP16X3) split_cmma<PREC>(A, B, cre[t], cim[t]);
+            else split_cmma<PREC>(A, B, acc_re[t], acc_im[t]);
+          }
+        }
+      }
+      if constexpr (PREC == MDD_PREC_FP16X3) {
+        const float inv = 1.f / (fp16_sd * fp16_sr);
+#pragma unroll
+        for (int t = 0; t < C::TPWV; ++t) {
+          acc_re[t] += cre[t] * inv;
+          acc_im[t] += cim[t] * inv;
+        }
+      }
+      __syncthreads();
+    }
+    // Split-K partials -> LDS, then the residual and the loss.
+    float2* s_part = s_buf;
+#pragma unroll
+    for (int t = 0; t < C::TPWV; ++t) {
+      const int tile = g + t * C::G;
+      const int mt = tile / TNB, nt = tile % TNB;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = mt * 16 + lq * 4 + e, col = nt * 16 + lr;
+        s_part[(ks * MB + row) * NW + col] = make_float2(acc_re[t][e], acc_im[t][e]);
+      }
+    }
+    __syncthreads();
+    const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
+    double lpart = 0.0;
+    for (int i = tid; i < MB * NW; i += 256) {
+      const int row = i / NW, col = i % NW;
+      float2 z = s_part[row * NW + col];
+#pragma unroll
+      for (int s = 1; s < C::S; ++s) z = cadd(z, s_part[(s * MB + row) * NW + col]);
+      const int vs = blk0 * CB + col;
+      const bool ok = row < a.nb && vs < a.nvs && s_idx[row] >= 0;
+      if constexpr (KIND == GK_FUSED) {
+        if (ok) {
+          const float2 u = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
+          z = csub(z, u);
+          lpart += wk * ((double)z.x * z.x + (double)z.y * z.y);
+        } else {
+          z = make_float2(0.f, 0.f);
+        }
+        s_res[row * C::RST + col] = z;
+      } else {  // GK_FWD: predicted data spectra of the batch
+        const int blk = blk0 + col / 16;
+        if (row < a.nb && blk < a.nvb)
+          a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)] =
+              ok ? z : make_float2(0.f, 0.f);
+      }
+    }
+    if constexpr (KIND == GK_FUSED) {
+      const double tot = block_sum256(lpart, s_red);
+      if (tid == 0) a.loss_part[logical] = tot;
+    }
+    if constexpr (KIND == GK_FWD) return;
+  } else {
+    // Adjoint only: the batch spectra V_k are the right-hand operand.
+    for (int i = tid; i < MB * NW; i += 256) {
+      const int row = i / NW, col = i % NW;
+      const int blk = blk0 + col / 16;
+      float2 z = make_float2(0.f, 0.f);
+      if (row < a.nb && blk < a.nvb && s_idx[row] >= 0)
+        z = a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)];
+      s_res[row * C::RST + col] = z;
+    }
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ adjoint
+  float fp16_ss = 1.f;
+  if constexpr (PREC == MDD_PREC_FP16X3) fp16_ss = chunk_scale(s_res, MB, C::RST, NW);
+  for (int r0 = 0; r0 < a.nr; r0 += KCH) {
+    load_d_chunk(r0);
+    __syncthreads();
+    if constexpr (PREC == MDD_PREC_FP16X3) fp16_sd = chunk_scale(s_d, MB, C::DST, KCH);
+#pragma unroll
+    for (int mi = 0; mi < C::MT_PER_WAVE; ++mi) {
+      const int mt = wave * C::MT_PER_WAVE + mi;
+#pragma unroll
+      for (int nt = 0; nt < TNB; ++nt) {
+        floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (!C::SPLIT) {
+#pragma unroll
+          for (int kk = 0; kk < MB / 4; ++kk) {
+            const float2 dv = s_d[(kk * 4 + lq) * C::DST + mt * 16 + lr];
+            const float2 sv = s_res[(kk * 4 + lq) * C::RST + nt * 16 + lr];
+            re = mfma4(dv.x, sv.x, re);
+            re = mfma4(dv.y, sv.y, re);
+            im = mfma4(dv.x, sv.y, im);
+            im = mfma4(-dv.y, sv.x, im);
+          }
+        } else {
+          using Op = SplitOp<PREC>;
+#pragma unroll
+          for (int kk = 0; kk < (MB + 31) / 32; ++kk) {
+            Op A, B;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int b = kk * 32 + lq * 8 + e;
+              float2 dv = make_float2(0.f, 0.f), sv = make_float2(0.f, 0.f);
+              if (b < MB) {
+                dv = cconj(s_d[b * C::DST + mt * 16 + lr]);
+                sv = s_res[b * C::RST + nt * 16 + lr];
+              }
+              if constexpr (PREC == MDD_PREC_FP16X3) {
+                dv = cscale(dv, fp16_sd);
+                sv = cscale(sv, fp16_ss);
+              }
+              A.set(e, dv);
+              B.set(e, sv);
+            }
+            split_cmma<PREC>(A, B, re, im);
+          }
+          if constexpr (PREC == MDD_PREC_FP16X3) {
+            const float inv = 1.f / (fp16_sd * fp16_ss);
+            re *= inv;
+            im *= inv;
+          }
+        }
+        const int blk = blk0 + nt;
+        if (blk < a.nvb) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = r0 + mt * 16 + lq * 4 + e;
+            if (r < a.nr)
+              a.F[(((size_t)r * a.nvb + blk) * a.nf + k) * CB + lr] = make_float2(re[e], im[e]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int PREC, int NBT, int TNB>
+hipError_t launch_cfg(int kind, const GemmArgs& a, hipStream_t s) {
+  using C = GemmCfg<PREC, NBT, TNB>;
+  const int ncg = (a.nvb + TNB - 1) / TNB;
+  const dim3 grid(a.nf * ncg), block(256);
+  const size_t sm = C::SMEM;
+  switch (kind) {
+    case GK_FUSED:
+      if (sm > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm<PREC, NBT, TNB, GK_FUSED>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      hipLaunchKernelGGL((k_gemm<PREC, NBT, TNB, GK_FUSED>), grid, block, sm, s, a);
+      break;
+    case GK_FWD:
+      if (sm > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm<PREC, NBT, TNB, GK_FWD>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      hipLaunchKernelGGL((k_gemm<PREC, NBT, TNB, GK_FWD>), grid, block, sm, s, a);
+      break;
+    case GK_ADJ:
+      if (sm > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm<PREC, NBT, TNB, GK_ADJ>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      hipLaunchKernelGGL((k_gemm<PREC, NBT, TNB, GK_ADJ>), grid, block, sm, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
+  if (a.nb <= 16) return launch_cfg<PREC, 1, 1>(kind, a, s);
+  if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
+  return launch_cfg<PREC, 4, 4>(kind, a, s);
+}
+
+}  // namespace
+
+hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s) {
+  if (a.nb <= 0 || a.nb > NB_LIMIT) return hipErrorInvalidValue;
+  switch (precision) {
+    case MDD_PREC_FP32: return launch_prec<MDD_PREC_FP32>(kind, a, s);
+    case MDD_PREC_BF16X3: return launch_prec<MDD_PREC_BF16X3>(kind, a, s);
+    case MDD_PREC_FP16X3: return launch_prec<MDD_PREC_FP16X3>(kind, a, s);
+    case MDD_PREC_BF16: return launch_prec<MDD_PREC_BF16>(kind, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mdd

@@ -1,0 +1,93 @@
+// Internal declarations shared by the host layer (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "mdd.h"
+
+namespace mdd {
+
+// Frequency-domain traces are stored in blocks of CB consecutive columns
+// (virtual sources, or receivers for the kernel); a block of one row holds
+// [nf][CB] complex values, 128 bytes per frequency.
+constexpr int CB = 16;
+constexpr int NB_LIMIT = 64;  // largest batch: D_b rows and residuals live in LDS
+constexpr int KC = 64;        // receiver chunk of the per-frequency products
+
+enum TraceMode : int {
+  TM_RFFT = 0,        // time -> spectra (+ optional out-of-band energy)
+  TM_IRFFT = 1,       // spectra -> time
+  TM_GRAD = 2,        // spectra -> time, mask, ||g||^2
+  TM_SGD = 3,         // spectra -> gradient -> SGD update of the model
+  TM_ADAM = 4,        // ... Adam update
+  TM_NSGD = 5,        // ... Nesterov-momentum update
+};
+
+// One launch of the trace kernel: a grid of tiles, tile (row, cb) holding the
+// traces (row, cb*CB + c), c < CB, of a [rows][ncols][nt] time-domain array.
+// Spectral element (row, cb, k, c) lives at spec[row*s_row + cb*s_cb + k*s_k + c].
+struct TraceArgs {
+  int nt, nf, rows, ncols, ncb;
+  const float* x_in;      // TM_RFFT input
+  const float* x_in2;     // TM_RFFT: optional second input, transformed is x_in + mu2 * x_in2
+  float mu2;
+  float* x_out;           // TM_IRFFT / TM_GRAD output
+  float2* spec;
+  long long s_row, s_cb, s_k;
+  float* model;           // update modes: R (in place)
+  float* st0;             // first optimiser state (Adam m / Nesterov velocity)
+  float* st1;             // second optimiser state (Adam v)
+  float lr, beta1, beta2, eps, mu, inv_bc1, inv_bc2;
+  int store_spec;         // update modes: write spectra of the next evaluation point
+  const int32_t* onset;   // [rows][ncols] or NULL
+  double* part;           // per-tile float64 partial: out-of-band energy or ||g||^2
+  const float2* tw;       // exp(-2 pi i m / nt), m < nt
+};
+
+enum GemmKind : int {
+  GK_FUSED = 0,   // Res = D_b R_k - U_b (loss partials); G_k = D_b^H Res, written over R_k
+  GK_FWD = 1,     // P_k = D_b R_k -> batch spectra
+  GK_ADJ = 2,     // G_k = D_b^H V_k, V from batch spectra
+};
+
+struct GemmArgs {
+  const float2* Df;       // [nf][ns][nrp]
+  const float2* Uf;       // [nf][ns][nvsp]
+  float2* F;              // [nr][nvb][nf][CB]   model / gradient spectra
+  float2* Bsp;            // [nb][nvb][nf][CB]   batch spectra
+  const int32_t* idx;
+  double* loss_part;      // [gridDim.x * gridDim.y]
+  int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
+};
+
+struct ReduceArgs {
+  const double* loss_part;
+  int n_loss;
+  double loss_scale;      // 1 / (2 nt)
+  const double* oob;      // [ns] per-source out-of-band energy (already / (2 nt))
+  const int32_t* idx;
+  int nb, ns;
+  const double* gn_part;
+  int n_gn;
+  double* loss_out;
+  double* gnorm2_out;
+};
+
+hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s);
+hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s);
+hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
+                          hipStream_t s);
+hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,
+                        double* lam_out, hipStream_t s);
+
+// Blocks of ncols columns.
+inline int nblocks(int ncols) { return (ncols + CB - 1) / CB; }
+inline int round16(int n) { return nblocks(n) * CB; }
+
+}  // namespace mdd

@@ -1,0 +1,142 @@
+// Float64 reductions (loss, gradient norm, out-of-band data energy) and the
+// per-frequency power iteration for the largest singular value of the kernel.
+// Every sum runs in a fixed order (no atomics), so results are bitwise
+// reproducible run to run.
+#include "device_common.h"
+#include "mdd_internal.h"
+
+namespace mdd {
+namespace {
+
+// loss = scale * sum(loss partials) + sum_b oob[idx[b]];  gnorm2 = sum(gnorm partials).
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+  __shared__ double red[4];
+  double l = 0.0;
+  for (int i = threadIdx.x; i < a.n_loss; i += 256) l += a.loss_part[i];
+  l = block_sum256(l, red);
+  double g = 0.0;
+  for (int i = threadIdx.x; i < a.n_gn; i += 256) g += a.gn_part[i];
+  g = block_sum256(g, red);
+  if (threadIdx.x == 0) {
+    double o = 0.0;
+    if (a.oob) {
+      for (int b = 0; b < a.nb; ++b) {
+        const int s = a.idx[b];
+        if (s >= 0 && s < a.ns) o += a.oob[s];
+      }
+    }
+    if (a.loss_out) a.loss_out[0] = l * a.loss_scale + o;
+    if (a.gnorm2_out) a.gnorm2_out[0] = g;
+  }
+}
+
+__global__ void k_row_sum(const double* part, int rows, int cols, double scale, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < rows) {
+    double s = 0.0;
+    for (int c = 0; c < cols; ++c) s += part[(size_t)r * cols + c];
+    out[r] = s * scale;
+  }
+}
+
+// Power iteration on D_k^H D_k (all ns sources) for one frequency per
+// workgroup.  Returns the Rayleigh quotient ||D_k v||^2 of the final unit v.
+__global__ __launch_bounds__(256) void k_sigma(const float2* Df, int ns, int nr, int nrp, int iters,
+                                               double* lam_out) {
+  extern __shared__ double smem_d[];
+  double* vr = smem_d;            // [nr] real / imag of v (then of z)
+  double* vi = vr + nr;
+  double* yr = vi + nr;           // [ns]
+  double* yi = yr + ns;
+  __shared__ double red[4];
+  __shared__ double bc;
+  const int k = blockIdx.x;
+  const float2* D = Df + (size_t)k * ns * nrp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  double n2 = 0.0;
+  for (int r = tid; r < nr; r += 256) {  // deterministic, non-degenerate start
+    vr[r] = 1.0 + 0.25 * (double)((r * 37) % 11);
+    vi[r] = 0.1 * (double)((r * 17) % 7);
+    n2 += vr[r] * vr[r] + vi[r] * vi[r];
+  }
+  n2 = block_sum256(n2, red);
+  if (tid == 0) bc = 1.0 / sqrt(n2);
+  __syncthreads();
+  for (int r = tid; r < nr; r += 256) {
+    vr[r] *= bc;
+    vi[r] *= bc;
+  }
+  __syncthreads();
+
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    double ynorm = 0.0;
+    for (int s = wave; s < ns; s += 4) {  // y = D v
+      double ar = 0.0, ai = 0.0;
+      for (int r = lane; r < nr; r += 64) {
+        const float2 d = D[(size_t)s * nrp + r];
+        ar += (double)d.x * vr[r] - (double)d.y * vi[r];
+        ai += (double)d.x * vi[r] + (double)d.y * vr[r];
+      }
+      ar = wave_sum(ar);
+      ai = wave_sum(ai);
+      if (lane == 0) {
+        yr[s] = ar;
+        yi[s] = ai;
+        ynorm += ar * ar + ai * ai;
+      }
+    }
+    ynorm = block_sum256(ynorm, red);
+    if (tid == 0) bc = ynorm;
+    __syncthreads();
+    lam = bc;
+    double z2 = 0.0;
+    for (int r = tid; r < nr; r += 256) {  // z = D^H y, written over v
+      double zr = 0.0, zi = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        const float2 d = D[(size_t)s * nrp + r];
+        zr += (double)d.x * yr[s] + (double)d.y * yi[s];
+        zi += (double)d.x * yi[s] - (double)d.y * yr[s];
+      }
+      vr[r] = zr;
+      vi[r] = zi;
+      z2 += zr * zr + zi * zi;
+    }
+    z2 = block_sum256(z2, red);
+    if (tid == 0) bc = z2 > 0.0 ? 1.0 / sqrt(z2) : 0.0;
+    __syncthreads();
+    for (int r = tid; r < nr; r += 256) {
+      vr[r] *= bc;
+      vi[r] *= bc;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) lam_out[k] = lam;
+}
+
+}  // namespace
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_row_sum, dim3((rows + 255) / 256), dim3(256), 0, s, part, rows, cols, scale,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,
+                        double* lam_out, hipStream_t s) {
+  const size_t sm = sizeof(double) * 2 * ((size_t)nr + ns);
+  if (sm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(k_sigma, dim3(nf), dim3(256), sm, s, Df, ns, nr, nrp, iters, lam_out);
+  return hipGetLastError();
+}
+
+}  // namespace mdd

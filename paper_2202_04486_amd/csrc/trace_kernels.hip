@@ -1,0 +1,438 @@
+// Time <-> frequency kernels over traces: the model / data transforms of the
+// MDC operator (Appendix A: Fourier transform along time before, inverse
+// transform after, the per-frequency products) fused with the causality mask,
+// the float64 gradient norm and the optimiser update.
+//
+// A real trace of nt samples is transformed as a complex sequence of
+// N2 = nt/2 points z[n] = x[2n] + i x[2n+1] (then split into the one-sided
+// spectrum), with a radix-8 Stockham FFT held in registers: each lane owns 8
+// points n = j + L r (L = N2/8 lanes per trace, r < 8), passes exchange data
+// through a wave-private LDS region.  A workgroup owns one tile of 16 traces
+// whose spectra form one contiguous [nf][16] block in HBM, staged in LDS so
+// both the time side (whole traces) and the frequency side (whole blocks) are
+// read and written with contiguous accesses.
+#include "device_common.h"
+#include "mdd_internal.h"
+
+namespace mdd {
+namespace {
+
+constexpr int SPS = CB + 1;  // LDS row stride of a spectral tile (odd -> no bank aliasing)
+
+template <bool INV>
+__device__ __forceinline__ float2 rot(float2 a) {  // * -i (forward) or * +i (inverse)
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 twid(const float2* tw, int m) {
+  const float2 w = tw[m];
+  return INV ? make_float2(w.x, -w.y) : w;
+}
+
+// In-register 8-point DFT (radix-2 decomposition), sign by direction.
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  const float h = 0.70710678118654752440f;
+  const float2 a0 = cadd(v[0], v[4]), a1 = csub(v[0], v[4]);
+  const float2 a2 = cadd(v[2], v[6]), a3 = csub(v[2], v[6]);
+  const float2 a4 = cadd(v[1], v[5]), a5 = csub(v[1], v[5]);
+  const float2 a6 = cadd(v[3], v[7]), a7 = csub(v[3], v[7]);
+  const float2 e0 = cadd(a0, a2), e2 = csub(a0, a2);
+  const float2 e1 = cadd(a1, rot<INV>(a3)), e3 = csub(a1, rot<INV>(a3));
+  const float2 o0 = cadd(a4, a6), o2 = csub(a4, a6);
+  const float2 o1 = cadd(a5, rot<INV>(a7)), o3 = csub(a5, rot<INV>(a7));
+  float2 t1, t3;
+  if (!INV) {
+    t1 = make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+    t3 = make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+  } else {
+    t1 = make_float2(h * (o1.x - o1.y), h * (o1.x + o1.y));
+    t3 = make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y));
+  }
+  const float2 t2 = rot<INV>(o2);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }  // LDS padding
+
+template <int N2>
+struct FftShape {
+  static constexpr int L = N2 / 8;
+  static constexpr int NP8 = N2 >= 512 ? 3 : 2;                 // radix-8 passes
+  static constexpr int REM = N2 / (NP8 == 3 ? 512 : 64);         // 1, 2 or 4: tail radix
+  static constexpr int SC = N2 + N2 / 8;                         // padded scratch per trace
+  static_assert(N2 == 64 || N2 == 128 || N2 == 256 || N2 == 512, "unsupported length");
+};
+
+// Complex FFT of N2 = NT/2 points of one trace.  On entry lane j holds
+// v[r] = a[j + L r]; on exit v[r] = A[j + L r] (natural order, unnormalised).
+template <int NT, bool INV>
+__device__ __forceinline__ void fft_half(float2 (&v)[8], int j, float2* sc, const float2* tw) {
+  constexpr int N2 = NT / 2;
+  using S = FftShape<N2>;
+  constexpr int L = S::L;
+#pragma unroll
+  for (int p = 0; p < S::NP8; ++p) {
+    const int Ns = p == 0 ? 1 : (p == 1 ? 8 : 64);
+    if (p > 0) {
+      const int k = j & (Ns - 1);
+      const int step = NT / (8 * Ns);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twid<INV>(tw, r * k * step));
+    }
+    dft8<INV>(v);
+    const bool last = (p == S::NP8 - 1) && (S::REM == 1);
+    if (!last) {
+      const int base = (j / Ns) * Ns * 8 + (j & (Ns - 1));
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) sc[pidx(base + r * Ns)] = v[r];
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = sc[pidx(j + r * L)];
+    }
+  }
+  if constexpr (S::REM == 4) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int jj = j + L * h;
+      float2 x0 = v[h], x1 = v[h + 2], x2 = v[h + 4], x3 = v[h + 6];
+      x1 = cmul(x1, twid<INV>(tw, 2 * jj));
+      x2 = cmul(x2, twid<INV>(tw, 4 * jj));
+      x3 = cmul(x3, twid<INV>(tw, 6 * jj));
+      const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+      const float2 s13 = cadd(x1, x3), d13 = rot<INV>(csub(x1, x3));
+      v[h] = cadd(s02, s13);
+      v[h + 4] = csub(s02, s13);
+      v[h + 2] = cadd(d02, d13);
+      v[h + 6] = csub(d02, d13);
+    }
+  } else if constexpr (S::REM == 2) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int jj = j + L * h;
+      const float2 x0 = v[h];
+      const float2 x1 = cmul(v[h + 4], twid<INV>(tw, 2 * jj));
+      v[h] = cadd(x0, x1);
+      v[h + 4] = csub(x0, x1);
+    }
+  }
+}
+
+// Split the half-length complex spectrum Z into the one-sided spectrum of the
+// real trace: X[k] = (Z[k] + conj Z[N2-k])/2 - i W^k (Z[k] - conj Z[N2-k])/2,
+// W = exp(-2 pi i / nt).  On exit v[r] = X[j + L r]; lane j = 0 also returns
+// the Nyquist bin X[N2].
+template <int NT>
+__device__ __forceinline__ void rfft_split(float2 (&v)[8], int j, int lane, const float2* tw,
+                                           float2& xnyq) {
+  constexpr int N2 = NT / 2;
+  constexpr int L = N2 / 8;
+  const int pj = (L - j) & (L - 1);
+  const int plane = lane - j + pj;
+  float2 zp[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const float2 a = v[7 - r];
+    const float2 b = v[(8 - r) & 7];
+    float2 s;
+    s.x = __shfl(a.x, plane, 64);
+    s.y = __shfl(a.y, plane, 64);
+    zp[r] = (j == 0) ? b : s;
+  }
+  xnyq = make_float2(v[0].x - v[0].y, 0.f);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = j + L * r;
+    const float2 A = v[r], B = cconj(zp[r]);
+    const float2 E = cscale(cadd(A, B), 0.5f);
+    const float2 Dh = cscale(csub(A, B), 0.5f);
+    const float2 O = make_float2(Dh.y, -Dh.x);  // -i * Dh
+    v[r] = cadd(E, cmul(tw[k], O));
+  }
+  if (j == 0) v[0].y = 0.f;
+}
+
+// Inverse of rfft_split: from the one-sided spectrum column c of a staged tile
+// (bins >= nf are zero) build Z[k] = E[k] + i O[k] for k = j + L r.
+template <int NT>
+__device__ __forceinline__ void irfft_merge(float2 (&v)[8], int j, const float2* spec, int c,
+                                            int nf, const float2* tw) {
+  constexpr int N2 = NT / 2;
+  constexpr int L = N2 / 8;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = j + L * r;
+    const int km = N2 - k;
+    float2 X = k < nf ? spec[k * SPS + c] : make_float2(0.f, 0.f);
+    float2 Xm = km < nf ? spec[km * SPS + c] : make_float2(0.f, 0.f);
+    if (k == 0) {  // the imaginary parts of the DC and Nyquist bins of a real trace are dropped
+      X.y = 0.f;
+      Xm.y = 0.f;
+    }
+    const float2 B = cconj(Xm);
+    const float2 E = cscale(cadd(X, B), 0.5f);
+    const float2 O = cmul(cscale(csub(X, B), 0.5f), cconj(tw[k]));
+    v[r] = make_float2(E.x - O.y, E.y + O.x);
+  }
+}
+
+template <int NT, int MODE>
+__global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
+  constexpr int N2 = NT / 2;
+  using S = FftShape<N2>;
+  constexpr int L = S::L;
+  constexpr int TPW = 64 / L;                       // traces per wavefront
+  constexpr int ITERS = (CB + 4 * TPW - 1) / (4 * TPW);
+  constexpr bool UPDATE = MODE == TM_SGD || MODE == TM_ADAM || MODE == TM_NSGD;
+  extern __shared__ float2 smem[];
+  float2* s_tw = smem;
+  float2* s_sc = smem + NT;
+  float2* s_spec = s_sc + 4 * TPW * S::SC;
+  __shared__ double s_red[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = lane / L, j = lane % L;
+  const int row = blockIdx.x / a.ncb, cb = blockIdx.x % a.ncb;
+  const int nf = a.nf;
+  float2* gspec = a.spec + row * a.s_row + cb * a.s_cb;
+
+  for (int i = tid; i < NT; i += 256) s_tw[i] = a.tw[i];
+  if (MODE != TM_RFFT) {
+    for (int i = tid; i < nf * CB; i += 256) {
+      const int k = i >> 4, c = i & (CB - 1);
+      s_spec[k * SPS + c] = gspec[k * a.s_k + c];
+    }
+  }
+  __syncthreads();
+
+  float2* sc = s_sc + (wave * TPW + p) * S::SC;
+  double part = 0.0;
+  const float inv_n2 = 1.0f / float(N2);
+
+#pragma unroll 1
+  for (int it = 0; it < ITERS; ++it) {
+    const int c = it * 4 * TPW + wave * TPW + p;
+    const int col = cb * CB + c;
+    const bool in_tile = c < CB;
+    const bool valid = in_tile && col < a.ncols;
+    const long long trace = (long long)row * a.ncols + col;
+    float2 v[8];
+
+    if constexpr (MODE == TM_RFFT) {
+      const float2* x = reinterpret_cast<const float2*>(a.x_in + trace * NT);
+      const float2* x2 = reinterpret_cast<const float2*>(a.x_in2 + trace * NT);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        float2 z = make_float2(0.f, 0.f);
+        if (valid) {
+          z = x[j + L * r];
+          if (a.x_in2) {
+            const float2 y = x2[j + L * r];
+            z.x += a.mu2 * y.x;
+            z.y += a.mu2 * y.y;
+          }
+        }
+        v[r] = z;
+      }
+      fft_half<NT, false>(v, j, sc, s_tw);
+      float2 xn;
+      rfft_split<NT>(v, j, lane, s_tw, xn);
+      if (in_tile) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int k = j + L * r;
+          if (k < nf) s_spec[k * SPS + c] = v[r];
+        }
+        if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
+      }
+      if (a.part && valid) {  // energy in the bins that are not retained
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int k = j + L * r;
+          if (k >= nf) part += 2.0 * ((double)v[r].x * v[r].x + (double)v[r].y * v[r].y);
+        }
+        if (j == 0 && nf <= N2) part += (double)xn.x * xn.x;
+      }
+    } else {
+      if (in_tile) irfft_merge<NT>(v, j, s_spec, c, nf, s_tw);
+      else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = make_float2(0.f, 0.f);
+      }
+      fft_half<NT, true>(v, j, sc, s_tw);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = cscale(v[r], inv_n2);  // time samples 2n, 2n+1
+
+      if constexpr (MODE == TM_IRFFT) {
+        if (valid) {
+          float2* y = reinterpret_cast<float2*>(a.x_out + trace * NT);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) y[j + L * r] = v[r];
+        }
+      } else {
+        const int t0 = (a.onset && valid) ? a.onset[trace] : 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int t = 2 * (j + L * r);
+          if (t < t0) v[r].x = 0.f;
+          if (t + 1 < t0) v[r].y = 0.f;
+          if (valid) part += (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+        }
+        if constexpr (MODE == TM_GRAD) {
+          if (valid) {
+            float2* y = reinterpret_cast<float2*>(a.x_out + trace * NT);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) y[j + L * r] = v[r];
+          }
+        } else if constexpr (UPDATE) {
+          float2* R = reinterpret_cast<float2*>(a.model + trace * NT);
+          float2* M0 = reinterpret_cast<float2*>(a.st0 + trace * NT);
+          float2* M1 = reinterpret_cast<float2*>(a.st1 + trace * NT);
+          float2 nxt[8];
+          if (valid) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+              const int n = j + L * r;
+              const float2 g = v[r];
+              float2 rv = R[n];
+              float2 ev;
+              if constexpr (MODE == TM_SGD) {
+                rv.x -= a.lr * g.x;
+                rv.y -= a.lr * g.y;
+              } else if constexpr (MODE == TM_ADAM) {
+                float2 m = M0[n], s = M1[n];
+                m.x = a.beta1 * m.x + (1.f - a.beta1) * g.x;
+                m.y = a.beta1 * m.y + (1.f - a.beta1) * g.y;
+                s.x = a.beta2 * s.x + (1.f - a.beta2) * g.x * g.x;
+                s.y = a.beta2 * s.y + (1.f - a.beta2) * g.y * g.y;
+                rv.x -= a.lr * (m.x * a.inv_bc1) / (sqrtf(s.x * a.inv_bc2) + a.eps);
+                rv.y -= a.lr * (m.y * a.inv_bc1) / (sqrtf(s.y * a.inv_bc2) + a.eps);
+                M0[n] = m;
+                M1[n] = s;
+              } else {  // Nesterov: velocity <- mu velocity - lr g; R <- R + velocity
+                float2 vel = M0[n];
+                vel.x = a.mu * vel.x - a.lr * g.x;
+                vel.y = a.mu * vel.y - a.lr * g.y;
+                const int t = 2 * n;
+                if (t < t0) vel.x = 0.f;
+                if (t + 1 < t0) vel.y = 0.f;
+                rv.x += vel.x;
+                rv.y += vel.y;
+                M0[n] = vel;
+                ev = make_float2(rv.x + a.mu * vel.x, rv.y + a.mu * vel.y);
+              }
+              const int t = 2 * n;
+              if (t < t0) rv.x = 0.f;
+              if (t + 1 < t0) rv.y = 0.f;
+              R[n] = rv;
+              if constexpr (MODE == TM_NSGD) {
+                if (t < t0) ev.x = 0.f;
+                if (t + 1 < t0) ev.y = 0.f;
+                nxt[r] = ev;
+              } else {
+                nxt[r] = rv;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) nxt[r] = make_float2(0.f, 0.f);
+          }
+          if (a.store_spec) {  // spectra of the next evaluation point, over this column
+            fft_half<NT, false>(nxt, j, sc, s_tw);
+            float2 xn;
+            rfft_split<NT>(nxt, j, lane, s_tw, xn);
+            if (in_tile) {
+#pragma unroll
+              for (int r = 0; r < 8; ++r) {
+                const int k = j + L * r;
+                if (k < nf) s_spec[k * SPS + c] = nxt[r];
+              }
+              if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (a.part) {
+    const double tot = block_sum256(part, s_red);
+    if (tid == 0) a.part[blockIdx.x] = tot;
+  }
+  if (MODE == TM_RFFT || (UPDATE && a.store_spec)) {
+    __syncthreads();
+    for (int i = tid; i < nf * CB; i += 256) {
+      const int k = i >> 4, c = i & (CB - 1);
+      gspec[k * a.s_k + c] = s_spec[k * SPS + c];
+    }
+  }
+}
+
+__global__ void k_twiddles(float2* tw, int nt) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < nt) {
+    double s, c;
+    sincospi(-2.0 * (double)m / (double)nt, &s, &c);
+    tw[m] = make_float2((float)c, (float)s);
+  }
+}
+
+template <int NT>
+size_t trace_smem(int nf) {
+  constexpr int N2 = NT / 2;
+  constexpr int TPW = 64 / (N2 / 8);
+  return sizeof(float2) * ((size_t)NT + 4 * TPW * FftShape<N2>::SC + (size_t)nf * SPS);
+}
+
+template <int NT, int MODE>
+hipError_t launch_mode(const TraceArgs& a, hipStream_t s) {
+  const dim3 grid(a.rows * a.ncb), block(256);
+  const size_t sm = trace_smem<NT>(a.nf);
+  if (sm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trace<NT, MODE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL((k_trace<NT, MODE>), grid, block, sm, s, a);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_nt(int mode, const TraceArgs& a, hipStream_t s) {
+  switch (mode) {
+    case TM_RFFT: return launch_mode<NT, TM_RFFT>(a, s);
+    case TM_IRFFT: return launch_mode<NT, TM_IRFFT>(a, s);
+    case TM_GRAD: return launch_mode<NT, TM_GRAD>(a, s);
+    case TM_SGD: return launch_mode<NT, TM_SGD>(a, s);
+    case TM_ADAM: return launch_mode<NT, TM_ADAM>(a, s);
+    case TM_NSGD: return launch_mode<NT, TM_NSGD>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3((nt + 255) / 256), dim3(256), 0, s, tw, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s) {
+  if (a.rows <= 0 || a.ncb <= 0) return hipSuccess;
+  switch (a.nt) {
+    case 128: return launch_nt<128>(mode, a, s);
+    case 256: return launch_nt<256>(mode, a, s);
+    case 512: return launch_nt<512>(mode, a, s);
+    case 1024: return launch_nt<1024>(mode, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mdd

@@ -208,3 +208,22 @@ def model_draw(wl: Workload, shape, rng=None) -> np.ndarray:
     """Standard-normal model / probe arrays (derivative checks start from these)."""
     rng = rng or streams(wl.seed)[4]
     return rng.standard_normal(shape)
+
+
+def random_arrays(seed: int, *shapes, dtype=np.float64):
+    """Independent standard-normal arrays (one child stream per shape) for
+    derivative checks and parity cases that need no physical structure."""
+    kids = np.random.SeedSequence(seed).spawn(len(shapes))
+    return [np.random.default_rng(k).standard_normal(s).astype(dtype) for k, s in zip(kids, shapes)]
+
+
+def random_batch(ns: int, nb: int, seed: int, replace: bool = False) -> np.ndarray:
+    """A sorted batch of nb source indices drawn from range(ns) (int32)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(ns, size=nb, replace=replace or nb > ns)).astype(np.int32)
+
+
+def random_onsets(nr: int, nvs: int, nt: int, seed: int) -> np.ndarray:
+    """Mask onsets drawn uniformly from [0, nt/2) per trace (int32), for mask tests
+    that need no geometry."""
+    return np.random.default_rng(seed).integers(0, nt // 2, size=(nr, nvs)).astype(np.int32)

@@ -1,0 +1,112 @@
+"""The C-ABI library loads, exports every entry point of include/mdd.h, and
+validates arguments on the host before any HIP call (runs without a GPU)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2202_04486_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdd.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:mdd|mdc)_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIB_PATH):
+        pytest.fail("libmdd.so is not built (run `python -m paper_2202_04486_amd.build`)")
+    return native.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 15
+    assert set(names) == set(native.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_header_is_plain_c():
+    res = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+
+
+def dims(**kw):
+    base = dict(ns=32, nr=24, nvs=20, nt=128, nf=65, nb_max=8, precision="fp32", flags=0)
+    base.update(kw)
+    return native.make_dims(**base)
+
+
+def test_workspace_bytes_valid_and_monotone(lib):
+    a = native.workspace_bytes(dims())
+    b = native.workspace_bytes(dims(nvs=40))
+    assert a > 0 and b > a and a % 256 == 0
+
+
+@pytest.mark.parametrize("kw", [dict(nf=66), dict(nt=100), dict(nt=2048), dict(nb_max=33),
+                                dict(ns=100, nb_max=65), dict(ns=0), dict(nr=-1), dict(nf=0),
+                                dict(precision=7), dict(flags=2), dict(nvs=5000)])
+def test_invalid_dims_rejected(lib, kw):
+    assert native.workspace_bytes(dims(**kw)) == 0
+    out = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1 << 12)
+    st = lib.mdd_plan_create(ctypes.byref(dims(**kw)), ctypes.addressof(buf), 1 << 12, None,
+                             ctypes.byref(out))
+    assert st in (native.MDD_ESHAPE, native.MDD_EINVAL, native.MDD_EUNSUPPORTED)
+    assert not out.value
+
+
+def test_plan_create_workspace_checks(lib):
+    d = dims()
+    need = native.workspace_bytes(d)
+    out = ctypes.c_void_p()
+    assert lib.mdd_plan_create(ctypes.byref(d), None, need, None, ctypes.byref(out)) == native.MDD_ENOMEM
+    assert lib.mdd_plan_create(ctypes.byref(d), ctypes.c_void_p(4096), need - 1, None,
+                               ctypes.byref(out)) == native.MDD_ENOMEM
+    assert lib.mdd_plan_create(ctypes.byref(d), ctypes.c_void_p(4096 + 8), need, None,
+                               ctypes.byref(out)) == native.MDD_ENOMEM
+    assert lib.mdd_plan_create(ctypes.byref(d), ctypes.c_void_p(4096), need, None, None) == native.MDD_EINVAL
+    assert lib.mdd_plan_create(None, ctypes.c_void_p(4096), need, None, ctypes.byref(out)) == native.MDD_EINVAL
+
+
+def test_null_plan_rejected_everywhere(lib):
+    p = ctypes.c_void_p(8)
+    opt = native.Opt(1, 0, 1e-2, 0.9, 0.999, 1e-8, 0.9, 1)
+    E = native.MDD_EINVAL
+    assert lib.mdd_plan_destroy(None) == E
+    assert lib.mdd_plan_set_stream(None, None) == E
+    assert lib.mdd_set_kernel(None, p) == E
+    assert lib.mdd_set_data(None, p) == E
+    assert lib.mdd_set_mask(None, p) == E
+    assert lib.mdc_forward(None, p, p, 1, p) == E
+    assert lib.mdc_adjoint(None, p, p, 1, p) == E
+    assert lib.mdd_stoch_grad(None, p, p, 1, p, p, p) == E
+    assert lib.mdd_step(None, p, p, p, ctypes.byref(opt), p, 1, p, p) == E
+    assert lib.mdd_invalidate_model_spectra(None) == E
+    assert lib.mdd_sigma_max2(None, 10, p) == E
+    assert lib.mdd_profile_enable(None, 1, 10) == E
+    assert lib.mdd_plan_last_hip_error(None) == 0
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = native.status_string(code)
+        assert isinstance(s, str) and s
+    assert native.status_string(-99) == "unknown status"
+
+
+def test_plan_refuses_cpu_device():
+    from paper_2202_04486_amd.plan import Plan
+    with pytest.raises(ValueError):
+        Plan(8, 8, 8, 128, 65, 4, device="cpu")

@@ -1,0 +1,75 @@
+"""The named workloads at their full sizes, in the configuration the benchmark
+times: the tiny 2D case over its whole 10-epoch SGD run, and the 201-trace 2D
+line (Adam, batches of 16, mask, stored model spectra) over its first steps."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import freq, optim, stepsize
+
+from gpu_helpers import H, T, f32, make_plan, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tiny2d_sgd_trajectory():
+    wl = synth.WORKLOADS["tiny2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u = f32(freq.mdc(d, f32(p["r_true"]), wl.nf))           # noise-free
+    s2, _ = stepsize.sigma_max2_kernel(d, wl.nf)
+    lr = 1.0 / s2
+    plan = make_plan(d, u, nb_max=wl.nb, nf=wl.nf)
+    R = torch.zeros(wl.nr, wl.nvs, wl.nt, device="cuda")
+    ro = np.zeros((wl.nr, wl.nvs, wl.nt))
+    losses = []
+    for perm in synth.epoch_permutations(wl, wl.epochs):
+        for b in optim.batches(perm, wl.nb):
+            loss, _ = plan.mdd_step(R, T(b, torch.int32), opt="sgd", lr=lr)
+            lo, g = freq.batch_loss_grad(d, ro, u, b, wl.nf)
+            assert abs(loss.item() - lo) <= 1e-5 * lo
+            losses.append(lo)
+            ro = optim.sgd(ro, g, lr)
+        assert relerr(H(R), ro) <= 1e-5
+    assert losses[-1] < 0.2 * losses[0]                     # it is converging
+
+
+@pytest.fixture(scope="module")
+def line2d():
+    wl = synth.WORKLOADS["line2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u_clean = freq.mdc(d, f32(p["r_true"]), wl.nf)
+    u = f32(u_clean + synth.scale_noise(u_clean, p["noise"], wl.snr_db))
+    return wl, d, u, p["onset"]
+
+
+def test_line2d_gradient_full_size(line2d):
+    wl, d, u, onset = line2d
+    plan = make_plan(d, u, onset=onset, nb_max=wl.nb, nf=wl.nf)
+    b = optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb)[0]
+    r = f32(synth.model_draw(wl, (wl.nr, wl.nvs, wl.nt)))
+    G, loss, gn = plan.mdd_stoch_grad(T(r), T(b, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, b, wl.nf)
+    go = optim.apply_mask(go, onset)
+    assert relerr(H(G), go) <= 1e-5
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    assert abs(gn.item() - np.sum(go * go)) <= 2e-5 * np.sum(go * go)
+
+
+def test_line2d_adam_steps_full_size(line2d):
+    wl, d, u, onset = line2d
+    plan = make_plan(d, u, onset=onset, nb_max=wl.nb, nf=wl.nf, store_rf=True)
+    R = torch.zeros(wl.nr, wl.nvs, wl.nt, device="cuda")
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    ro = np.zeros((wl.nr, wl.nvs, wl.nt))
+    mo, vo = np.zeros_like(ro), np.zeros_like(ro)
+    bs = optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb)
+    for t, b in enumerate(bs[:4], start=1):
+        loss, _ = plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=1e-2, s0=m, s1=v, t=t)
+        lo, g = freq.batch_loss_grad(d, ro, u, b, wl.nf)
+        assert abs(loss.item() - lo) <= 1e-5 * lo
+        ro, mo, vo = optim.adam(ro, mo, vo, optim.apply_mask(g, onset), t, 1e-2, onset=onset)
+    assert relerr(H(m), mo) <= 1e-4
+    assert relerr(H(R), ro) <= 1e-4
