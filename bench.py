@@ -1,0 +1,309 @@
+#!/usr/bin/env python3
+"""Stochastic-MDD benchmark on one MI355X: gradient evaluations per second.
+
+A step is one `mdd_step` (model spectra [stored by the previous step], the
+fused per-frequency products with residual and loss, inverse transforms with
+mask, gradient norm and Adam update, float64 reductions) on one batch of
+sources of the synthetic 2D-line workload: 201 sources / receivers / virtual
+sources at 10 m, 1024 samples at 4 ms, 257 retained bins, Ricker 15 Hz,
+8 periodic down-going events, 5 reflections, 20 dB noise, batches of 16, Adam,
+causality mask.  The FP32 form gives `value`; the bf16 and fp16 split forms
+are timed on the same data and reported beside it with their gradient error
+against the FP64 oracle.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  Inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stochastic MDD grad evals/s + % MFMA roofline, BF16-split vs FP32 at stated err"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_adam_line2d.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_04486_amd", "csrc", "trace_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(wl, dev):
+    """d, R_true on the GPU from the closed-form events; noise from the seeded host stream."""
+    import torch
+
+    import synth
+    g = synth.streams(wl.seed)
+    xs, xr, xv = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl), synth.positions(wl.nvs, wl)
+    dev_ev, rev = synth.down_events(wl, g[0]), synth.reflection_events(wl, g[1])
+    d = torch.empty((wl.ns, wl.nr, wl.nt), dtype=torch.float32, device=dev)
+    chunk = max(1, (1 << 26) // (wl.nr * wl.nt))
+    for s0 in range(0, wl.ns, chunk):
+        rows = np.arange(s0, min(wl.ns, s0 + chunk))
+        d[rows[0]:rows[-1] + 1] = synth.event_cube(xs, xr, wl.nt, wl.dt, wl.f0, dev_ev, rows=rows,
+                                                   xp=torch, device=dev, dtype=torch.float32)
+    r_true = torch.empty((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
+    chunk = max(1, (1 << 26) // (wl.nvs * wl.nt))
+    for s0 in range(0, wl.nr, chunk):
+        rows = np.arange(s0, min(wl.nr, s0 + chunk))
+        r_true[rows[0]:rows[-1] + 1] = synth.event_cube(xr, xv, wl.nt, wl.dt, wl.f0, rev, rows=rows,
+                                                        xp=torch, device=dev, dtype=torch.float32)
+    noise = None
+    if wl.snr_db is not None:
+        noise = torch.from_numpy(g[2].standard_normal((wl.ns, wl.nvs, wl.nt), dtype=np.float32)).to(dev)
+    return d, r_true, noise, synth.onsets(wl)
+
+
+def up_going(plan, r_true, noise, wl, dev):
+    """u = P+ R_true with the library's forward operator, plus noise at the stated SNR."""
+    import torch
+    u = torch.empty((wl.ns, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
+    nb = plan.nb_max
+    for s0 in range(0, wl.ns, nb):
+        idx = torch.arange(s0, min(wl.ns, s0 + nb), dtype=torch.int32, device=dev)
+        plan.mdc_forward(r_true, idx, out=u[s0:s0 + idx.numel()])
+    if noise is not None:
+        eu = float((u.double() ** 2).sum())
+        en = float((noise.double() ** 2).sum())
+        u += noise * math.sqrt(eu / (en * 10.0 ** (wl.snr_db / 10.0)))
+    return u
+
+
+def step_tables(wl, nb, n_steps, dev):
+    """The batch sequence of as many epochs as needed, on the device."""
+    import torch
+
+    import synth
+    from paper_2202_04486_amd.solver import epoch_index_table
+    spe = math.ceil(wl.ns / nb)
+    perms = synth.epoch_permutations(wl, math.ceil(n_steps / spe) + 1)
+    tabs, lens = [], []
+    for p in perms:
+        t, ln = epoch_index_table(p, nb)
+        tabs.append(t)
+        lens.append(ln)
+    return torch.from_numpy(np.concatenate(tabs)).to(dev), np.concatenate(lens), spe
+
+
+def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2):
+    import torch
+
+    from paper_2202_04486_amd.plan import Plan
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, precision=form, store_rf=True, device=dev)
+    plan.mdd_set_kernel(d)
+    plan.mdd_set_data(u)
+    plan.mdd_set_mask(onset_t)
+    R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    loss = torch.zeros(warmup + steps, dtype=torch.float64, device=dev)
+    gn = torch.zeros_like(loss)
+
+    def step(j):
+        plan.mdd_step(R, idx_tab[j, :lens[j]], opt="adam", lr=lr, s0=m, s1=v, t=j + 1,
+                      loss_out=loss[j:j + 1], gnorm2_out=gn[j:j + 1])
+
+    for j in range(warmup):
+        step(j)
+    torch.cuda.synchronize()
+    plan.profile_enable(True, capacity=8 * steps + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(warmup, warmup + steps):
+        step(j)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    losses = loss.cpu().numpy()
+    return plan, R, elapsed, prof, losses
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the update kernel from the committed counter summary,
+    or None if it is missing or the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.strip().startswith("- "):
+            k, _, v = line.strip()[2:].partition(":")
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_hash(KERNEL_SOURCE):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
+    """The FP64 oracle, as it stands, timed on the host cores on a bounded sample
+    of the same workload (Adam steps on the first batches), and the gradient
+    error of each GPU form against it at the GPU's current model."""
+    from oracle import freq, optim
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    d64 = d.double().cpu().numpy()
+    u64 = u.double().cpu().numpy()
+    r_eval = R_gpu.double().cpu().numpy()
+    errs = {}
+    lo, go = freq.batch_loss_grad(d64, r_eval, u64, idx0, wl.nf)
+    go = optim.apply_mask(go, onset)
+    nrm = np.linalg.norm(go)
+    for form, g in grads.items():
+        errs[form] = float(np.linalg.norm(g.double().cpu().numpy() - go) / nrm)
+    import synth
+    bs = optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb)
+    r = np.zeros((wl.nr, wl.nvs, wl.nt))
+    m = np.zeros_like(r)
+    v = np.zeros_like(r)
+    n = 0
+    t0 = time.perf_counter()
+    while n < len(bs) and (time.perf_counter() - t0) < budget_s:
+        _, g = freq.batch_loss_grad(d64, r, u64, bs[n], wl.nf)
+        r, m, v = optim.adam(r, m, v, optim.apply_mask(g, onset), n + 1, 1e-2, onset=onset)
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "grad evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} Adam steps (batches of {wl.nb}) of the first epoch of the 201-trace "
+                      f"line, oracle.freq gradient + oracle.optim.adam in float64, {el:.1f} s"}, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=130)
+    ap.add_argument("--warmup", type=int, default=13)
+    ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    wl = synth.WORKLOADS["line2d"]
+    dev = torch.device("cuda", 0)
+    log("generating inputs")
+    d, r_true, noise, onset = make_inputs(wl, dev)
+    onset_t = torch.from_numpy(onset).to(dev)
+    from paper_2202_04486_amd.plan import Plan
+    p0 = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, device=dev)
+    p0.mdd_set_kernel(d)
+    u = up_going(p0, r_true, noise, wl, dev)
+    del p0
+    idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + args.steps, dev)
+    torch.cuda.synchronize()
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    forms = [f for f in args.forms.split(",") if f]
+    if "fp32" not in forms:
+        forms.insert(0, "fp32")
+    res, grads = {}, {}
+    idx0 = idx_tab[0, :lens[0]]
+    R_eval = None
+    for form in forms:
+        log(f"timing {form}")
+        plan, R, el, prof, losses = run_form(form, wl, d, u, onset_t, idx_tab, lens,
+                                             args.warmup, args.steps, dev)
+        if R_eval is None:
+            R_eval = R.clone()
+        g, _, _ = plan.mdd_stoch_grad(R_eval, idx0)
+        grads[form] = g.clone()
+        res[form] = {"elapsed": el, "prof": prof, "loss_first": float(losses[0]),
+                     "loss_last": float(losses[-1])}
+        del plan
+        torch.cuda.synchronize()
+
+    K = args.steps
+    fp = res["fp32"]
+    value = K / fp["elapsed"]
+    ms_step = 1e3 * fp["elapsed"] / K
+    Mt = wl.nr * wl.nvs * wl.nt
+    nb = wl.nb
+
+    def per_launch(prof, name):
+        ms, cnt = prof[name]
+        return (ms / cnt) if cnt else 0.0
+
+    cls_ms = {k: per_launch(fp["prof"], k) for k in fp["prof"]}
+    dominant = max(cls_ms, key=lambda k: cls_ms[k] * fp["prof"][k][1])
+    upd_ms = cls_ms["update"]
+    upd_bytes = 24.0 * Mt                      # R, m, v read and written (float32)
+    traffic = stored_traffic()
+    roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
+                "achieved": upd_bytes / (upd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": traffic}
+    roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
+    gemm_flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
+
+    def gemm_roof(form):
+        ms = per_launch(res[form]["prof"], "gemm")
+        hw = gemm_flops * (3 if form in ("bf16x3", "fp16x3") else 1)
+        return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
+                "mfma_tflops": hw / (ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS[form],
+                "frac": hw / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[form]}
+
+    alg_bytes = 24.0 * Mt + 2 * 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * wl.nvs * wl.nf
+    out = {
+        "metric": METRIC, "value": value, "unit": "grad evals/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "line2d: ns=nr=nvs=201 (10 m line), nt=1024 (4 ms), nf=257, "
+                               "batch 16, Adam, causality mask, 20 dB noise, stored model spectra",
+                   "global_batch": nb, "seq_len": wl.nt, "parallelism": "none (1 GPU)"},
+        "epoch_ms": ms_step * spe,
+        "steps_per_epoch": spe,
+        "kernel_ms": cls_ms,
+        "dominant_kernel": dominant,
+        "roofline": roofline,
+        "method_roofline_frac": (alg_bytes / HBM_PEAK_GBS / 1e9) / (ms_step * 1e-3),
+        "gemm_roofline": {f: gemm_roof(f) for f in forms},
+        "forms": {f: {"value": K / res[f]["elapsed"], "ms_per_step": 1e3 * res[f]["elapsed"] / K,
+                      "speedup_vs_fp32": fp["elapsed"] / res[f]["elapsed"],
+                      "gemm_speedup_vs_fp32": per_launch(fp["prof"], "gemm") /
+                      max(per_launch(res[f]["prof"], "gemm"), 1e-12)} for f in forms},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        cb, errs = cpu_baseline(wl, d, u, onset, R_eval, grads, idx0.cpu().numpy(), args.cpu_budget)
+        out["cpu_baseline"] = cb
+        for f in forms:
+            out["forms"][f]["grad_rel_err_vs_fp64_oracle"] = errs[f]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -373,6 +373,8 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
   a.beta2 = (float)o.beta2;
   a.eps = (float)o.eps;
   a.mu = (float)o.mu;
+  a.omb1 = (float)(1.0 - o.beta1);
+  a.omb2 = (float)(1.0 - o.beta2);
   if (mode == TM_ADAM) {
     a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(o.beta1, (double)o.t)));
     a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(o.beta2, (double)o.t)));

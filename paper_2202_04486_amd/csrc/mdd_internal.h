@@ -42,6 +42,7 @@ struct TraceArgs {
   float* st0;             // first optimiser state (Adam m / Nesterov velocity)
   float* st1;             // second optimiser state (Adam v)
   float lr, beta1, beta2, eps, mu, inv_bc1, inv_bc2;
+  float omb1, omb2;       // 1 - beta1, 1 - beta2 rounded once from double
   int store_spec;         // update modes: write spectra of the next evaluation point
   const int32_t* onset;   // [rows][ncols] or NULL
   double* part;           // per-tile float64 partial: out-of-band energy or ||g||^2

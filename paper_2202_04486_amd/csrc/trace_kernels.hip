@@ -310,10 +310,10 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 rv.y -= a.lr * g.y;
               } else if constexpr (MODE == TM_ADAM) {
                 float2 m = M0[n], s = M1[n];
-                m.x = a.beta1 * m.x + (1.f - a.beta1) * g.x;
-                m.y = a.beta1 * m.y + (1.f - a.beta1) * g.y;
-                s.x = a.beta2 * s.x + (1.f - a.beta2) * g.x * g.x;
-                s.y = a.beta2 * s.y + (1.f - a.beta2) * g.y * g.y;
+                m.x = a.beta1 * m.x + a.omb1 * g.x;
+                m.y = a.beta1 * m.y + a.omb1 * g.y;
+                s.x = a.beta2 * s.x + a.omb2 * (g.x * g.x);
+                s.y = a.beta2 * s.y + a.omb2 * (g.y * g.y);
                 rv.x -= a.lr * (m.x * a.inv_bc1) / (sqrtf(s.x * a.inv_bc2) + a.eps);
                 rv.y -= a.lr * (m.y * a.inv_bc1) / (sqrtf(s.y * a.inv_bc2) + a.eps);
                 M0[n] = m;

@@ -58,7 +58,7 @@ def test_line2d_gradient_full_size(line2d):
     assert abs(gn.item() - np.sum(go * go)) <= 2e-5 * np.sum(go * go)
 
 
-def test_line2d_adam_steps_full_size(line2d):
+def _adam_run(line2d, eps, steps=4, lr=1e-2):
     wl, d, u, onset = line2d
     plan = make_plan(d, u, onset=onset, nb_max=wl.nb, nf=wl.nf, store_rf=True)
     R = torch.zeros(wl.nr, wl.nvs, wl.nt, device="cuda")
@@ -66,10 +66,33 @@ def test_line2d_adam_steps_full_size(line2d):
     ro = np.zeros((wl.nr, wl.nvs, wl.nt))
     mo, vo = np.zeros_like(ro), np.zeros_like(ro)
     bs = optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb)
-    for t, b in enumerate(bs[:4], start=1):
-        loss, _ = plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=1e-2, s0=m, s1=v, t=t)
+    for t, b in enumerate(bs[:steps], start=1):
+        loss, _ = plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=lr, s0=m, s1=v, t=t, eps=eps)
         lo, g = freq.batch_loss_grad(d, ro, u, b, wl.nf)
         assert abs(loss.item() - lo) <= 1e-5 * lo
-        ro, mo, vo = optim.adam(ro, mo, vo, optim.apply_mask(g, onset), t, 1e-2, onset=onset)
-    assert relerr(H(m), mo) <= 1e-4
-    assert relerr(H(R), ro) <= 1e-4
+        ro, mo, vo = optim.adam(ro, mo, vo, optim.apply_mask(g, onset), t, lr, eps=eps, onset=onset)
+    assert relerr(H(m), mo) <= 1e-5
+    assert relerr(H(v), vo) <= 1e-5
+    return np.abs(H(R) - ro), ro
+
+
+def test_line2d_adam_steps_full_size(line2d):
+    """Adam as the benchmark runs it (eps = 1e-8).  The moments are smooth in g and
+    match tightly.  The model moves by lr * m_hat / (sqrt(v_hat) + eps) per entry, a
+    normalisation that turns float32 rounding of a near-zero (or, across steps, nearly
+    cancelling) gradient entry into a visible change of that entry's step: those few
+    entries are bounded by the step size, all others agree far below it."""
+    lr = 1e-2
+    diff, _ = _adam_run(line2d, 1e-8, lr=lr)
+    assert np.median(diff) <= 1e-5 * lr
+    assert np.mean(diff > 1e-2 * lr) <= 1e-2
+    assert diff.max() <= 2 * 4 * lr
+
+
+def test_line2d_adam_smooth_eps_full_size(line2d):
+    """With eps at 1 % of the gradient's rms the update is Lipschitz in g, and every
+    entry of the model must follow the oracle."""
+    lr = 1e-2
+    diff, ro = _adam_run(line2d, 16.0, lr=lr)
+    assert np.linalg.norm(diff) <= 1e-4 * np.linalg.norm(ro)
+    assert diff.max() <= 1e-2 * lr
