@@ -98,11 +98,12 @@ def step_tables(wl, nb, n_steps, dev):
     return torch.from_numpy(np.concatenate(tabs)).to(dev), np.concatenate(lens), spe
 
 
-def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2):
+def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2, store_rf=True):
     import torch
 
     from paper_2202_04486_amd.plan import Plan
-    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, precision=form, store_rf=True, device=dev)
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, precision=form, store_rf=store_rf,
+                device=dev)
     plan.mdd_set_kernel(d)
     plan.mdd_set_data(u)
     plan.mdd_set_mask(onset_t)
@@ -198,6 +199,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-store-rf", action="store_true",
+                    help="recompute the model spectra at each step instead of storing them")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -237,7 +240,8 @@ def main():
     for form in forms:
         log(f"timing {form}")
         plan, R, el, prof, losses = run_form(form, wl, d, u, onset_t, idx_tab, lens,
-                                             args.warmup, args.steps, dev)
+                                             args.warmup, args.steps, dev,
+                                             store_rf=not args.no_store_rf)
         if R_eval is None:
             R_eval = R.clone()
         g, _, _ = plan.mdd_stoch_grad(R_eval, idx0)

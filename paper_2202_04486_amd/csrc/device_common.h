@@ -41,4 +41,27 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return s;
 }
 
+// Sum of n doubles by one workgroup of NTH threads in a fixed order (four
+// independent loads per thread per round, then a fixed tree): bitwise
+// reproducible.  `red` is LDS of NTH / 64 doubles; the result is in thread 0.
+template <int NTH>
+__device__ __forceinline__ double block_fixed_sum(const double* p, int n, double* red) {
+  double acc = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * NTH < n; i += 4 * NTH) {
+    const double x0 = p[i], x1 = p[i + NTH], x2 = p[i + 2 * NTH], x3 = p[i + 3 * NTH];
+    acc += (x0 + x1) + (x2 + x3);
+  }
+  for (; i < n; i += NTH) acc += p[i];
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NTH / 64; ++w) s += red[w];
+  return s;
+}
+
 }  // namespace mdd

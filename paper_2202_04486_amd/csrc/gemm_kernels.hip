@@ -8,7 +8,8 @@
 //
 // A workgroup owns one frequency k and a group of TNB column blocks (16
 // virtual sources each).  Its batch rows of D_k are gathered by index into
-// LDS in receiver chunks of KC, the residual block stays in LDS between the
+// LDS in receiver chunks (the whole receiver range when it fits: one global
+// round trip), the residual block stays in LDS between the
 // two products, and R_k is read and G_k written exactly once.
 //
 // There is no complex MFMA: a complex product is four real products
@@ -120,34 +121,35 @@ template <int PREC, int NBT, int TNB>
 struct GemmCfg {
   static constexpr int MB = NBT * 16;                 // padded batch rows
   static constexpr int NW = TNB * 16;                 // columns per workgroup
-  static constexpr int TILES = NBT * TNB;
+  static constexpr int TILES = NBT * TNB;             // 16x16 output tiles of the forward product
   static constexpr int S = TILES >= 4 ? 1 : 4 / TILES;  // waves splitting K
   static constexpr int G = 4 / S;                     // wave groups over tiles
   static constexpr int TPWV = TILES / G;              // tiles per wave
   static constexpr bool SPLIT = PREC != MDD_PREC_FP32;
-  static constexpr int KSTEP = SPLIT ? 32 : 4;
-  static constexpr int KC_ = (SPLIT && S == 4) ? 128 : KC;   // receiver chunk
-  static constexpr int DST = KC_ + 2;                 // LDS row stride of D (16-byte aligned)
-  static constexpr int RST = NW + 1;                  // LDS row stride of R / residual
-  static constexpr int RS_SZ = KC_ * RST;
-  static constexpr int RED_SZ = S * MB * NW;
-  static constexpr int BUF_SZ = RS_SZ > RED_SZ ? RS_SZ : RED_SZ;
-  static constexpr int MT_ADJ = KC_ / 16;             // adjoint m-tiles per chunk
-  static constexpr int MT_PER_WAVE = MT_ADJ / 4;
-  static constexpr size_t SMEM = sizeof(float2) * ((size_t)MB * DST + BUF_SZ + (size_t)MB * RST);
+  static constexpr int KSTEP = SPLIT ? 32 : 4;        // receivers per MFMA
+  static constexpr int KCMAX = NBT == 1 ? (SPLIT ? 256 : 224) : (NBT == 2 ? 128 : 64);  // receiver chunk
+  static constexpr int KSW = KCMAX / KSTEP / S;       // k-steps per wave per chunk
+  static constexpr int BREG = SPLIT ? 8 : 1;          // right-operand values per lane per k-step
+  static constexpr int DST = KCMAX + 2;               // LDS row stride of D (16-byte aligned)
+  static constexpr int RST = NW + 1;                  // LDS row stride of the residual
+  static constexpr int RED_SZ = S > 1 ? S * MB * NW : 0;
+  static constexpr size_t SMEM = sizeof(float2) * ((size_t)MB * DST + RED_SZ + (size_t)MB * RST);
+  static_assert(TILES % G == 0 && KCMAX % (KSTEP * S) == 0, "tiling");
+  // Tiles of one wave share their column tile when TILES >= 4 (tile = g + t * G).
+  static_assert(S > 1 || G % TNB == 0, "a wave's tiles must share one column tile");
 };
 
 template <int PREC, int NBT, int TNB, int KIND>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   using C = GemmCfg<PREC, NBT, TNB>;
-  constexpr int MB = C::MB, NW = C::NW, KCH = C::KC_;
+  constexpr int MB = C::MB, NW = C::NW, KCMAX = C::KCMAX, KSTEP = C::KSTEP;
   extern __shared__ float2 smem[];
-  float2* s_d = smem;                       // [MB][DST]
-  float2* s_buf = s_d + MB * C::DST;        // R chunk [KC][RST]  |  split-K partials [S][MB][NW]
-  float2* s_res = s_buf + C::BUF_SZ;        // residual [MB][RST]
+  float2* s_d = smem;                       // D_{b,k} chunk [MB][DST]
+  float2* s_part = s_d + MB * C::DST;       // split-K partials [S][MB][NW] (S > 1)
+  float2* s_res = s_part + C::RED_SZ;       // residual [MB][RST]
   __shared__ int s_idx[MB];
   __shared__ double s_red[4];
-  __shared__ float s_scale[4];              // fp16 split: D chunk, R chunk, residual scales
+  __shared__ float s_scale[4];              // fp16 split: per-chunk max-abs exchange
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
@@ -161,21 +163,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
   const int k = logical / ncg, cg = logical % ncg;
   const int blk0 = cg * TNB;
+  const int nchunks = (a.nr + KCMAX - 1) / KCMAX;
+  const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
 
-  for (int b = tid; b < MB; b += 256) {
-    int s = -1;
-    if (b < a.nb) {
-      s = a.idx[b];
-      if (s < 0 || s >= a.ns) s = -1;
+  auto fill_idx = [&]() {
+    for (int b = tid; b < MB; b += 256) {
+      int s = -1;
+      if (b < a.nb) {
+        s = a.idx[b];
+        if (s < 0 || s >= a.ns) s = -1;
+      }
+      s_idx[b] = s;
     }
-    s_idx[b] = s;
-  }
-  __syncthreads();
+    __syncthreads();
+  };
+  if constexpr (KIND == GK_ADJ) fill_idx();
 
-  auto load_d_chunk = [&](int r0) {
-    // D_{b,k}[b][r0 .. r0+KCH) -> s_d; rows b >= nb / bad index and r >= nr are zero.
-    for (int i = tid; i < MB * (KCH / 2); i += 256) {
-      const int b = i / (KCH / 2), rr = 2 * (i % (KCH / 2));
+  // Rows r0 .. r0 + lenp of D_{b,k} -> s_d (zero beyond nr and for bad indices).
+  auto load_d_chunk = [&](int r0, int lenp) {
+    for (int i = tid; i < MB * (lenp / 2); i += 256) {
+      const int b = i / (lenp / 2), rr = 2 * (i % (lenp / 2));
       const int s = s_idx[b];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (s >= 0 && r0 + rr < a.nr)
@@ -185,13 +192,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     }
   };
 
-  float fp16_sd = 1.f, fp16_sr = 1.f;   // used by the fp16 split form only
-  auto chunk_scale = [&](const float2* base, int rows, int stride, int cols) -> float {
-    float m = 0.f;
-    for (int i = tid; i < rows * cols; i += 256) {
-      const float2 z = base[(i / cols) * stride + (i % cols)];
-      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
-    }
+  auto block_amax_scale = [&](float m) -> float {  // fp16 split: power-of-two scale of a block
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
     if (lane == 0) s_scale[wave] = m;
@@ -200,72 +201,134 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     __syncthreads();
     return pow2_scale(amax);
   };
+  auto lds_amax = [&](const float2* base, int rows, int stride, int cols) -> float {
+    float m = 0.f;
+    for (int i = tid; i < rows * cols; i += 256) {
+      const float2 z = base[(i / cols) * stride + (i % cols)];
+      m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+    }
+    return m;
+  };
+
+  int last_r0 = -1;  // receiver chunk resident in s_d
 
   // ------------------------------------------------------------ forward
   if constexpr (KIND != GK_ADJ) {
+    const int g = wave % C::G, ks = wave / C::G;
+    const int nt_w = g % TNB;                       // column tile of this wave (S == 1)
+    // Right operand (R_k rows of this wave's k-steps), straight from HBM into
+    // registers: each load instruction reads 4 rows x 16 columns = 4 x 128 B.
+    // With S > 1 every wave uses the single column tile 0.
+    float2 bfr[C::KSW][C::BREG];
+    const int ncol_blk = blk0 + (C::S == 1 ? nt_w : 0);
+    auto load_b = [&](int r0, int len) {
+#pragma unroll
+      for (int q = 0; q < C::KSW; ++q) {
+        const int kk = ks + q * C::S;
+#pragma unroll
+        for (int e = 0; e < C::BREG; ++e) {
+          const int rr = kk * KSTEP + (C::SPLIT ? lq * 8 + e : lq);
+          float2 v = make_float2(0.f, 0.f);
+          if (rr < len && ncol_blk < a.nvb)
+            v = a.F[(((size_t)(r0 + rr) * a.nvb + ncol_blk) * a.nf + k) * CB + lr];
+          bfr[q][e] = v;
+        }
+      }
+    };
+    load_b(0, min(KCMAX, a.nr));   // issued before the batch indices are known
+    fill_idx();
+    float2 upre[C::TPWV][4];                        // data entries subtracted later (S == 1)
+    float2 upre_s[(MB * NW + 255) / 256];           // the same for S > 1
+    if constexpr (KIND == GK_FUSED && C::S > 1) {
+#pragma unroll
+      for (int q = 0; q < (MB * NW + 255) / 256; ++q) {
+        const int i = tid + 256 * q;
+        const int row = i / NW, col = i % NW;
+        const int vs = blk0 * CB + col;
+        upre_s[q] = make_float2(0.f, 0.f);
+        if (i < MB * NW && row < a.nb && vs < a.nvs && s_idx[row] >= 0)
+          upre_s[q] = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
+      }
+    }
+    if constexpr (KIND == GK_FUSED && C::S == 1) {
+#pragma unroll
+      for (int t = 0; t < C::TPWV; ++t) {
+        const int mt = (g + t * C::G) / TNB;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = mt * 16 + lq * 4 + e, vs = (blk0 + nt_w) * CB + lr;
+          upre[t][e] = make_float2(0.f, 0.f);
+          if (row < a.nb && vs < a.nvs && s_idx[row] >= 0)
+            upre[t][e] = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
+        }
+      }
+    }
     floatx4 acc_re[C::TPWV], acc_im[C::TPWV];
 #pragma unroll
     for (int t = 0; t < C::TPWV; ++t) {
       acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    const int g = wave % C::G, ks = wave / C::G;
-    for (int r0 = 0; r0 < a.nr; r0 += KCH) {
-      load_d_chunk(r0);
-      float2* s_r = s_buf;
-      for (int i = tid; i < KCH * (NW / 2); i += 256) {
-        const int rr = i / (NW / 2), cc = 2 * (i % (NW / 2));
-        const int blk = blk0 + cc / 16;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r0 + rr < a.nr && blk < a.nvb)
-          v = *reinterpret_cast<const float4*>(
-              a.F + (((size_t)(r0 + rr) * a.nvb + blk) * a.nf + k) * CB + (cc & 15));
-        s_r[rr * C::RST + cc] = make_float2(v.x, v.y);
-        s_r[rr * C::RST + cc + 1] = make_float2(v.z, v.w);
+    for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
+      const int len = min(KCMAX, a.nr - r0);
+      const int lenp = (len + 31) & ~31;
+      if (r0 > 0) {
+        load_b(r0, len);
+        __syncthreads();
       }
+      load_d_chunk(r0, lenp);
+      last_r0 = r0;
       __syncthreads();
-      floatx4 cre[C::TPWV], cim[C::TPWV];   // fp16 split: per-chunk accumulators
+      float fp16_sd = 1.f, fp16_sr = 1.f;
+      floatx4 cre[C::TPWV], cim[C::TPWV];             // fp16 split: per-chunk accumulators
       if constexpr (PREC == MDD_PREC_FP16X3) {
-        fp16_sd = chunk_scale(s_d, MB, C::DST, KCH);
-        fp16_sr = chunk_scale(s_r, KCH, C::RST, NW);
+        fp16_sd = block_amax_scale(lds_amax(s_d, MB, C::DST, lenp));
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < C::KSW; ++q)
+#pragma unroll
+          for (int e = 0; e < C::BREG; ++e)
+            m = fmaxf(m, fmaxf(fabsf(bfr[q][e].x), fabsf(bfr[q][e].y)));
+        fp16_sr = block_amax_scale(m);
 #pragma unroll
         for (int t = 0; t < C::TPWV; ++t) {
           cre[t] = floatx4{0.f, 0.f, 0.f, 0.f};
           cim[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
       }
-      if constexpr (!C::SPLIT) {
-        for (int kk = ks; kk < KCH / 4; kk += C::S) {
+#pragma unroll
+      for (int q = 0; q < C::KSW; ++q) {
+        const int kk = ks + q * C::S;
+        if (kk * KSTEP >= lenp) break;
+        if constexpr (!C::SPLIT) {
+          const float2 rv = bfr[q][0];
 #pragma unroll
           for (int t = 0; t < C::TPWV; ++t) {
-            const int tile = g + t * C::G;
-            const int mt = tile / TNB, nt = tile % TNB;
+            const int mt = (g + t * C::G) / TNB;
             const float2 dv = s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq];
-            const float2 rv = s_r[(kk * 4 + lq) * C::RST + nt * 16 + lr];
             acc_re[t] = mfma4(dv.x, rv.x, acc_re[t]);
             acc_re[t] = mfma4(-dv.y, rv.y, acc_re[t]);
             acc_im[t] = mfma4(dv.x, rv.y, acc_im[t]);
             acc_im[t] = mfma4(dv.y, rv.x, acc_im[t]);
           }
-        }
-      } else {
-        using Op = SplitOp<PREC>;
-        for (int kk = ks; kk < KCH / 32; kk += C::S) {
+        } else {
+          using Op = SplitOp<PREC>;
+          Op B;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float2 rv = bfr[q][e];
+            if constexpr (PREC == MDD_PREC_FP16X3) rv = cscale(rv, fp16_sr);
+            B.set(e, rv);
+          }
 #pragma unroll
           for (int t = 0; t < C::TPWV; ++t) {
-            const int tile = g + t * C::G;
-            const int mt = tile / TNB, nt = tile % TNB;
-            Op A, B;
+            const int mt = (g + t * C::G) / TNB;
+            Op A;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               float2 dv = s_d[(mt * 16 + lr) * C::DST + kk * 32 + lq * 8 + e];
-              float2 rv = s_r[(kk * 32 + lq * 8 + e) * C::RST + nt * 16 + lr];
-              if constexpr (PREC == MDD_PREC_FP16X3) {
-                dv = cscale(dv, fp16_sd);
-                rv = cscale(rv, fp16_sr);
-              }
+              if constexpr (PREC == MDD_PREC_FP16X3) dv = cscale(dv, fp16_sd);
               A.set(e, dv);
-              B.set(e, rv);
             }
             if constexpr (PREC == MDD_PREC_FP16X3) split_cmma<PREC>(A, B, cre[t], cim[t]);
             else split_cmma<PREC>(A, B, acc_re[t], acc_im[t]);
@@ -280,44 +343,71 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
           acc_im[t] += cim[t] * inv;
         }
       }
-      __syncthreads();
     }
-    // Split-K partials -> LDS, then the residual and the loss.
-    float2* s_part = s_buf;
-#pragma unroll
-    for (int t = 0; t < C::TPWV; ++t) {
-      const int tile = g + t * C::G;
-      const int mt = tile / TNB, nt = tile % TNB;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = mt * 16 + lq * 4 + e, col = nt * 16 + lr;
-        s_part[(ks * MB + row) * NW + col] = make_float2(acc_re[t][e], acc_im[t][e]);
-      }
-    }
-    __syncthreads();
-    const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
+
+    // Residual (or predicted data) and the loss partial.
     double lpart = 0.0;
-    for (int i = tid; i < MB * NW; i += 256) {
-      const int row = i / NW, col = i % NW;
-      float2 z = s_part[row * NW + col];
+    if constexpr (C::S == 1) {
 #pragma unroll
-      for (int s = 1; s < C::S; ++s) z = cadd(z, s_part[(s * MB + row) * NW + col]);
-      const int vs = blk0 * CB + col;
-      const bool ok = row < a.nb && vs < a.nvs && s_idx[row] >= 0;
-      if constexpr (KIND == GK_FUSED) {
-        if (ok) {
-          const float2 u = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
-          z = csub(z, u);
-          lpart += wk * ((double)z.x * z.x + (double)z.y * z.y);
-        } else {
-          z = make_float2(0.f, 0.f);
+      for (int t = 0; t < C::TPWV; ++t) {
+        const int mt = (g + t * C::G) / TNB;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = mt * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+          const int vs = blk0 * CB + col;
+          const bool ok = row < a.nb && vs < a.nvs && s_idx[row] >= 0;
+          float2 z = make_float2(acc_re[t][e], acc_im[t][e]);
+          if constexpr (KIND == GK_FUSED) {
+            if (ok) {
+              z = csub(z, upre[t][e]);
+              lpart += wk * ((double)z.x * z.x + (double)z.y * z.y);
+            } else {
+              z = make_float2(0.f, 0.f);
+            }
+            s_res[row * C::RST + col] = z;
+          } else {
+            if (row < a.nb && blk0 + nt_w < a.nvb)
+              a.Bsp[(((size_t)row * a.nvb + blk0 + nt_w) * a.nf + k) * CB + lr] =
+                  ok ? z : make_float2(0.f, 0.f);
+          }
         }
-        s_res[row * C::RST + col] = z;
-      } else {  // GK_FWD: predicted data spectra of the batch
-        const int blk = blk0 + col / 16;
-        if (row < a.nb && blk < a.nvb)
-          a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)] =
-              ok ? z : make_float2(0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < C::TPWV; ++t) {
+        const int tile = g + t * C::G;
+        const int mt = tile / TNB, nt = tile % TNB;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = mt * 16 + lq * 4 + e, col = nt * 16 + lr;
+          s_part[(ks * MB + row) * NW + col] = make_float2(acc_re[t][e], acc_im[t][e]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < (MB * NW + 255) / 256; ++q) {
+        const int i = tid + 256 * q;
+        if (i >= MB * NW) break;
+        const int row = i / NW, col = i % NW;
+        float2 z = s_part[row * NW + col];
+#pragma unroll
+        for (int s = 1; s < C::S; ++s) z = cadd(z, s_part[(s * MB + row) * NW + col]);
+        const int vs = blk0 * CB + col;
+        const bool ok = row < a.nb && vs < a.nvs && s_idx[row] >= 0;
+        if constexpr (KIND == GK_FUSED) {
+          if (ok) {
+            z = csub(z, upre_s[q]);
+            lpart += wk * ((double)z.x * z.x + (double)z.y * z.y);
+          } else {
+            z = make_float2(0.f, 0.f);
+          }
+          s_res[row * C::RST + col] = z;
+        } else {
+          const int blk = blk0 + col / 16;
+          if (row < a.nb && blk < a.nvb)
+            a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)] =
+                ok ? z : make_float2(0.f, 0.f);
+        }
       }
     }
     if constexpr (KIND == GK_FUSED) {
@@ -340,14 +430,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
   // ------------------------------------------------------------ adjoint
   float fp16_ss = 1.f;
-  if constexpr (PREC == MDD_PREC_FP16X3) fp16_ss = chunk_scale(s_res, MB, C::RST, NW);
-  for (int r0 = 0; r0 < a.nr; r0 += KCH) {
-    load_d_chunk(r0);
-    __syncthreads();
-    if constexpr (PREC == MDD_PREC_FP16X3) fp16_sd = chunk_scale(s_d, MB, C::DST, KCH);
-#pragma unroll
-    for (int mi = 0; mi < C::MT_PER_WAVE; ++mi) {
-      const int mt = wave * C::MT_PER_WAVE + mi;
+  if constexpr (PREC == MDD_PREC_FP16X3)
+    fp16_ss = block_amax_scale(lds_amax(s_res, MB, C::RST, NW));
+  for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
+    const int len = min(KCMAX, a.nr - r0);
+    const int lenp = (len + 31) & ~31;
+    if (!(nchunks == 1 && last_r0 == r0)) {   // the single chunk is still resident
+      if (r0 > 0) __syncthreads();
+      load_d_chunk(r0, lenp);
+      __syncthreads();
+    }
+    float fp16_sd = 1.f;
+    if constexpr (PREC == MDD_PREC_FP16X3) fp16_sd = block_amax_scale(lds_amax(s_d, MB, C::DST, lenp));
+    for (int mt = wave; mt * 16 < len; mt += 4) {
 #pragma unroll
       for (int nt = 0; nt < TNB; ++nt) {
         floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -400,7 +495,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         }
       }
     }
-    __syncthreads();
   }
 }
 

@@ -16,7 +16,6 @@ namespace mdd {
 // [nf][CB] complex values, 128 bytes per frequency.
 constexpr int CB = 16;
 constexpr int NB_LIMIT = 64;  // largest batch: D_b rows and residuals live in LDS
-constexpr int KC = 64;        // receiver chunk of the per-frequency products
 
 enum TraceMode : int {
   TM_RFFT = 0,        // time -> spectra (+ optional out-of-band energy)
@@ -25,6 +24,19 @@ enum TraceMode : int {
   TM_SGD = 3,         // spectra -> gradient -> SGD update of the model
   TM_ADAM = 4,        // ... Adam update
   TM_NSGD = 5,        // ... Nesterov-momentum update
+};
+
+struct ReduceArgs {
+  const double* loss_part;
+  int n_loss;
+  double loss_scale;      // 1 / (2 nt)
+  const double* oob;      // [ns] per-source out-of-band energy (already / (2 nt))
+  const int32_t* idx;
+  int nb, ns;
+  const double* gn_part;
+  int n_gn;
+  double* loss_out;
+  double* gnorm2_out;
 };
 
 // One launch of the trace kernel: a grid of tiles, tile (row, cb) holding the
@@ -63,19 +75,6 @@ struct GemmArgs {
   const int32_t* idx;
   double* loss_part;      // [gridDim.x * gridDim.y]
   int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
-};
-
-struct ReduceArgs {
-  const double* loss_part;
-  int n_loss;
-  double loss_scale;      // 1 / (2 nt)
-  const double* oob;      // [ns] per-source out-of-band energy (already / (2 nt))
-  const int32_t* idx;
-  int nb, ns;
-  const double* gn_part;
-  int n_gn;
-  double* loss_out;
-  double* gnorm2_out;
 };
 
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s);

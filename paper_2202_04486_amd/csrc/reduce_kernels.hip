@@ -8,23 +8,27 @@
 namespace mdd {
 namespace {
 
+constexpr int RED_THREADS = 1024;
+
 // loss = scale * sum(loss partials) + sum_b oob[idx[b]];  gnorm2 = sum(gnorm partials).
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
-  __shared__ double red[4];
-  double l = 0.0;
-  for (int i = threadIdx.x; i < a.n_loss; i += 256) l += a.loss_part[i];
-  l = block_sum256(l, red);
-  double g = 0.0;
-  for (int i = threadIdx.x; i < a.n_gn; i += 256) g += a.gn_part[i];
-  g = block_sum256(g, red);
-  if (threadIdx.x == 0) {
+// The per-source constants are gathered by one thread each (no serial chain of
+// dependent loads) and added in batch order.
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(ReduceArgs a) {
+  __shared__ double red[RED_THREADS / 64];
+  __shared__ double s_oob[NB_LIMIT];
+  if (threadIdx.x < a.nb) {
     double o = 0.0;
     if (a.oob) {
-      for (int b = 0; b < a.nb; ++b) {
-        const int s = a.idx[b];
-        if (s >= 0 && s < a.ns) o += a.oob[s];
-      }
+      const int s = a.idx[threadIdx.x];
+      if (s >= 0 && s < a.ns) o = a.oob[s];
     }
+    s_oob[threadIdx.x] = o;
+  }
+  const double l = block_fixed_sum<RED_THREADS>(a.loss_part, a.n_loss, red);
+  const double g = block_fixed_sum<RED_THREADS>(a.gn_part, a.n_gn, red);
+  if (threadIdx.x == 0) {
+    double o = 0.0;
+    for (int b = 0; b < a.nb; ++b) o += s_oob[b];
     if (a.loss_out) a.loss_out[0] = l * a.loss_scale + o;
     if (a.gnorm2_out) a.gnorm2_out[0] = g;
   }
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sigma(const float2* Df, int ns, int nr,
 }  // namespace
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -185,45 +185,95 @@ __device__ __forceinline__ void irfft_merge(float2 (&v)[8], int j, const float2*
   }
 }
 
+template <int NT>
+struct TraceCfg {
+  static constexpr int N2 = NT / 2;
+  static constexpr int L = FftShape<N2>::L;
+  static constexpr int TPW = 64 / L;              // traces per wavefront at a time
+  // One tile of CB traces per workgroup.  At nt = 1024 eight wavefronts take two
+  // traces each in turn, which keeps the workgroup at <= 80 KB of LDS so that two
+  // workgroups share a CU and one's arithmetic overlaps the other's memory traffic.
+  static constexpr int NWAVES = NT == 1024 ? 8 : CB / TPW;
+  static constexpr int ITERS = CB / (NWAVES * TPW);
+  static constexpr int THREADS = 64 * NWAVES;
+};
+
+// Deterministic sum over the workgroup of one double per thread (result in thread 0).
+template <int NWAVES>
+__device__ __forceinline__ double tile_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NWAVES; ++w) s += red[w];
+  return s;
+}
+
+// One workgroup per tile of CB traces, one wavefront per trace (or several
+// traces per wavefront for short traces).  Update modes issue the loads of the
+// model and optimiser state before the spectral tile is staged, so their
+// latency overlaps the staging and the inverse transform.
 template <int NT, int MODE>
-__global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
-  constexpr int N2 = NT / 2;
+__global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
+  using C = TraceCfg<NT>;
+  constexpr int N2 = C::N2, L = C::L, TPW = C::TPW, NW = C::NWAVES, NTH = C::THREADS;
   using S = FftShape<N2>;
-  constexpr int L = S::L;
-  constexpr int TPW = 64 / L;                       // traces per wavefront
-  constexpr int ITERS = (CB + 4 * TPW - 1) / (4 * TPW);
   constexpr bool UPDATE = MODE == TM_SGD || MODE == TM_ADAM || MODE == TM_NSGD;
   extern __shared__ float2 smem[];
   float2* s_tw = smem;
   float2* s_sc = smem + NT;
-  float2* s_spec = s_sc + 4 * TPW * S::SC;
-  __shared__ double s_red[4];
+  float2* s_spec = s_sc + NW * TPW * S::SC;
+  __shared__ double s_red[NW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = lane / L, j = lane % L;
   const int row = blockIdx.x / a.ncb, cb = blockIdx.x % a.ncb;
   const int nf = a.nf;
   float2* gspec = a.spec + row * a.s_row + cb * a.s_cb;
+  auto column = [&](int it) { return it * NW * TPW + wave * TPW + p; };  // trace within the tile
 
-  for (int i = tid; i < NT; i += 256) s_tw[i] = a.tw[i];
+  // Model / optimiser state of the lane's trace in iteration `it`.
+  float2 rv[8], m0[8], m1[8];
+  auto load_state = [&](int it) {
+    if constexpr (UPDATE) {
+      const int col = cb * CB + column(it);
+      const bool valid = col < a.ncols;
+      const long long trace = (long long)row * a.ncols + col;
+      const float2* R = reinterpret_cast<const float2*>(a.model + trace * NT);
+      const float2* M0 = reinterpret_cast<const float2*>(a.st0 + trace * NT);
+      const float2* M1 = reinterpret_cast<const float2*>(a.st1 + trace * NT);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        rv[r] = valid ? R[j + L * r] : make_float2(0.f, 0.f);
+        if constexpr (MODE != TM_SGD) m0[r] = valid ? M0[j + L * r] : make_float2(0.f, 0.f);
+        if constexpr (MODE == TM_ADAM) m1[r] = valid ? M1[j + L * r] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  load_state(0);  // requested before the spectral tile is staged
+
+  for (int i = tid; i < NT; i += NTH) s_tw[i] = a.tw[i];
   if (MODE != TM_RFFT) {
-    for (int i = tid; i < nf * CB; i += 256) {
-      const int k = i >> 4, c = i & (CB - 1);
-      s_spec[k * SPS + c] = gspec[k * a.s_k + c];
+    for (int i = tid; i < nf * (CB / 2); i += NTH) {
+      const int k = i / (CB / 2), c2 = 2 * (i % (CB / 2));
+      const float4 z = *reinterpret_cast<const float4*>(gspec + k * a.s_k + c2);
+      s_spec[k * SPS + c2] = make_float2(z.x, z.y);
+      s_spec[k * SPS + c2 + 1] = make_float2(z.z, z.w);
     }
   }
   __syncthreads();
 
   float2* sc = s_sc + (wave * TPW + p) * S::SC;
   double part = 0.0;
-  const float inv_n2 = 1.0f / float(N2);
 
 #pragma unroll 1
-  for (int it = 0; it < ITERS; ++it) {
-    const int c = it * 4 * TPW + wave * TPW + p;
+  for (int it = 0; it < C::ITERS; ++it) {
+    const int c = column(it);
     const int col = cb * CB + c;
-    const bool in_tile = c < CB;
-    const bool valid = in_tile && col < a.ncols;
+    const bool valid = col < a.ncols;
     const long long trace = (long long)row * a.ncols + col;
     float2 v[8];
 
@@ -246,14 +296,12 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
       fft_half<NT, false>(v, j, sc, s_tw);
       float2 xn;
       rfft_split<NT>(v, j, lane, s_tw, xn);
-      if (in_tile) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int k = j + L * r;
-          if (k < nf) s_spec[k * SPS + c] = v[r];
-        }
-        if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
+      for (int r = 0; r < 8; ++r) {
+        const int k = j + L * r;
+        if (k < nf) s_spec[k * SPS + c] = v[r];
       }
+      if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
       if (a.part && valid) {  // energy in the bins that are not retained
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -263,12 +311,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         if (j == 0 && nf <= N2) part += (double)xn.x * xn.x;
       }
     } else {
-      if (in_tile) irfft_merge<NT>(v, j, s_spec, c, nf, s_tw);
-      else {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = make_float2(0.f, 0.f);
-      }
+      irfft_merge<NT>(v, j, s_spec, c, nf, s_tw);
       fft_half<NT, true>(v, j, sc, s_tw);
+      const float inv_n2 = 1.0f / float(N2);
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = cscale(v[r], inv_n2);  // time samples 2n, 2n+1
 
@@ -280,12 +325,17 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         }
       } else {
         const int t0 = (a.onset && valid) ? a.onset[trace] : 0;
+        if (t0 > 0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int t = 2 * (j + L * r);
-          if (t < t0) v[r].x = 0.f;
-          if (t + 1 < t0) v[r].y = 0.f;
-          if (valid) part += (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+          for (int r = 0; r < 8; ++r) {
+            const int t = 2 * (j + L * r);
+            if (t < t0) v[r].x = 0.f;
+            if (t + 1 < t0) v[r].y = 0.f;
+          }
+        }
+        if (valid) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) part += (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
         }
         if constexpr (MODE == TM_GRAD) {
           if (valid) {
@@ -294,85 +344,90 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             for (int r = 0; r < 8; ++r) y[j + L * r] = v[r];
           }
         } else if constexpr (UPDATE) {
-          float2* R = reinterpret_cast<float2*>(a.model + trace * NT);
-          float2* M0 = reinterpret_cast<float2*>(a.st0 + trace * NT);
-          float2* M1 = reinterpret_cast<float2*>(a.st1 + trace * NT);
-          float2 nxt[8];
+          // v[r] holds the masked gradient; it is replaced by the next evaluation point.
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const float2 g = v[r];
+            float2 x = rv[r];
+            float2 ev;
+            if constexpr (MODE == TM_SGD) {
+              x.x -= a.lr * g.x;
+              x.y -= a.lr * g.y;
+            } else if constexpr (MODE == TM_ADAM) {
+              float2 m = m0[r], q = m1[r];
+              m.x = a.beta1 * m.x + a.omb1 * g.x;
+              m.y = a.beta1 * m.y + a.omb1 * g.y;
+              q.x = a.beta2 * q.x + a.omb2 * (g.x * g.x);
+              q.y = a.beta2 * q.y + a.omb2 * (g.y * g.y);
+              // hardware square root and reciprocal (each within 1 ulp)
+              x.x -= a.lr * (m.x * a.inv_bc1) *
+                     __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(q.x * a.inv_bc2) + a.eps);
+              x.y -= a.lr * (m.y * a.inv_bc1) *
+                     __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(q.y * a.inv_bc2) + a.eps);
+              m0[r] = m;
+              m1[r] = q;
+            } else {  // Nesterov: velocity <- mu velocity - lr g; R <- R + velocity
+              const int t = 2 * (j + L * r);
+              float2 vel = m0[r];
+              vel.x = a.mu * vel.x - a.lr * g.x;
+              vel.y = a.mu * vel.y - a.lr * g.y;
+              if (t < t0) vel.x = 0.f;
+              if (t + 1 < t0) vel.y = 0.f;
+              x.x += vel.x;
+              x.y += vel.y;
+              m0[r] = vel;
+              ev = make_float2(x.x + a.mu * vel.x, x.y + a.mu * vel.y);
+            }
+            const int t = 2 * (j + L * r);
+            if (t < t0) x.x = 0.f;
+            if (t + 1 < t0) x.y = 0.f;
+            rv[r] = x;
+            if constexpr (MODE == TM_NSGD) {
+              if (t < t0) ev.x = 0.f;
+              if (t + 1 < t0) ev.y = 0.f;
+              v[r] = ev;
+            } else {
+              v[r] = x;
+            }
+          }
           if (valid) {
+            float2* R = reinterpret_cast<float2*>(a.model + trace * NT);
+            float2* M0 = reinterpret_cast<float2*>(a.st0 + trace * NT);
+            float2* M1 = reinterpret_cast<float2*>(a.st1 + trace * NT);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-              const int n = j + L * r;
-              const float2 g = v[r];
-              float2 rv = R[n];
-              float2 ev;
-              if constexpr (MODE == TM_SGD) {
-                rv.x -= a.lr * g.x;
-                rv.y -= a.lr * g.y;
-              } else if constexpr (MODE == TM_ADAM) {
-                float2 m = M0[n], s = M1[n];
-                m.x = a.beta1 * m.x + a.omb1 * g.x;
-                m.y = a.beta1 * m.y + a.omb1 * g.y;
-                s.x = a.beta2 * s.x + a.omb2 * (g.x * g.x);
-                s.y = a.beta2 * s.y + a.omb2 * (g.y * g.y);
-                rv.x -= a.lr * (m.x * a.inv_bc1) / (sqrtf(s.x * a.inv_bc2) + a.eps);
-                rv.y -= a.lr * (m.y * a.inv_bc1) / (sqrtf(s.y * a.inv_bc2) + a.eps);
-                M0[n] = m;
-                M1[n] = s;
-              } else {  // Nesterov: velocity <- mu velocity - lr g; R <- R + velocity
-                float2 vel = M0[n];
-                vel.x = a.mu * vel.x - a.lr * g.x;
-                vel.y = a.mu * vel.y - a.lr * g.y;
-                const int t = 2 * n;
-                if (t < t0) vel.x = 0.f;
-                if (t + 1 < t0) vel.y = 0.f;
-                rv.x += vel.x;
-                rv.y += vel.y;
-                M0[n] = vel;
-                ev = make_float2(rv.x + a.mu * vel.x, rv.y + a.mu * vel.y);
-              }
-              const int t = 2 * n;
-              if (t < t0) rv.x = 0.f;
-              if (t + 1 < t0) rv.y = 0.f;
-              R[n] = rv;
-              if constexpr (MODE == TM_NSGD) {
-                if (t < t0) ev.x = 0.f;
-                if (t + 1 < t0) ev.y = 0.f;
-                nxt[r] = ev;
-              } else {
-                nxt[r] = rv;
-              }
+              R[j + L * r] = rv[r];
+              if constexpr (MODE != TM_SGD) M0[j + L * r] = m0[r];
+              if constexpr (MODE == TM_ADAM) M1[j + L * r] = m1[r];
             }
-          } else {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) nxt[r] = make_float2(0.f, 0.f);
           }
           if (a.store_spec) {  // spectra of the next evaluation point, over this column
-            fft_half<NT, false>(nxt, j, sc, s_tw);
+            fft_half<NT, false>(v, j, sc, s_tw);
             float2 xn;
-            rfft_split<NT>(nxt, j, lane, s_tw, xn);
-            if (in_tile) {
+            rfft_split<NT>(v, j, lane, s_tw, xn);
 #pragma unroll
-              for (int r = 0; r < 8; ++r) {
-                const int k = j + L * r;
-                if (k < nf) s_spec[k * SPS + c] = nxt[r];
-              }
-              if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
+            for (int r = 0; r < 8; ++r) {
+              const int k = j + L * r;
+              if (k < nf) s_spec[k * SPS + c] = v[r];
             }
+            if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
           }
+          if (it + 1 < C::ITERS) load_state(it + 1);
         }
       }
     }
   }
 
   if (a.part) {
-    const double tot = block_sum256(part, s_red);
+    const double tot = tile_sum<NW>(part, s_red);
     if (tid == 0) a.part[blockIdx.x] = tot;
   }
   if (MODE == TM_RFFT || (UPDATE && a.store_spec)) {
     __syncthreads();
-    for (int i = tid; i < nf * CB; i += 256) {
-      const int k = i >> 4, c = i & (CB - 1);
-      gspec[k * a.s_k + c] = s_spec[k * SPS + c];
+    for (int i = tid; i < nf * (CB / 2); i += NTH) {
+      const int k = i / (CB / 2), c2 = 2 * (i % (CB / 2));
+      const float2 z0 = s_spec[k * SPS + c2], z1 = s_spec[k * SPS + c2 + 1];
+      *reinterpret_cast<float4*>(gspec + k * a.s_k + c2) = make_float4(z0.x, z0.y, z1.x, z1.y);
     }
   }
 }
@@ -388,14 +443,14 @@ __global__ void k_twiddles(float2* tw, int nt) {
 
 template <int NT>
 size_t trace_smem(int nf) {
-  constexpr int N2 = NT / 2;
-  constexpr int TPW = 64 / (N2 / 8);
-  return sizeof(float2) * ((size_t)NT + 4 * TPW * FftShape<N2>::SC + (size_t)nf * SPS);
+  using C = TraceCfg<NT>;
+  return sizeof(float2) * ((size_t)NT + (size_t)C::NWAVES * C::TPW * FftShape<C::N2>::SC +
+                           (size_t)nf * SPS);
 }
 
 template <int NT, int MODE>
 hipError_t launch_mode(const TraceArgs& a, hipStream_t s) {
-  const dim3 grid(a.rows * a.ncb), block(256);
+  const dim3 grid(a.rows * a.ncb), block(TraceCfg<NT>::THREADS);
   const size_t sm = trace_smem<NT>(a.nf);
   if (sm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trace<NT, MODE>),
