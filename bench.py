@@ -269,7 +269,8 @@ def main():
     traffic = stored_traffic()
     roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
                 "achieved": upd_bytes / (upd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "traffic": traffic}
+                "traffic": traffic, "traffic_unit": "HBM bytes per launch (counters)",
+                "algorithmic_bytes": upd_bytes}
     roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
     gemm_flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
 
