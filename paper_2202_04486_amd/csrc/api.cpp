@@ -32,7 +32,7 @@ Layout make_layout(const mdd_dims& d) {
     o += align256(bytes);
     return at;
   };
-  L.tw = take(c8 * d.nt);
+  L.tw = take(c8 * 2 * d.nt);  // twiddle tables (at most 2 nt entries)
   L.df = take(c8 * d.nf * d.ns * nrp);
   L.uf = take(c8 * d.nf * d.ns * nvsp);
   L.oob = take(sizeof(double) * d.ns);

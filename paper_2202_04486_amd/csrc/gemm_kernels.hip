@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   float2* s_part = s_d + MB * C::DST;       // split-K partials [S][MB][NW] (S > 1)
   float2* s_res = s_part + C::RED_SZ;       // residual [MB][RST]
   __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];          // element offset of row idx[b] of D_k (or -1)
   __shared__ double s_red[4];
   __shared__ float s_scale[4];              // fp16 split: per-chunk max-abs exchange
 
@@ -165,6 +166,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   const int blk0 = cg * TNB;
   const int nchunks = (a.nr + KCMAX - 1) / KCMAX;
   const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
+  // F element (r, blk, k, c) is at r * rowstride + (blk * nf + k) * CB + c.
+  const long long rowstride = (long long)a.nvb * a.nf * CB;
 
   auto fill_idx = [&]() {
     for (int b = tid; b < MB; b += 256) {
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         if (s < 0 || s >= a.ns) s = -1;
       }
       s_idx[b] = s;
+      s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
     }
     __syncthreads();
   };
@@ -181,12 +185,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
   // Rows r0 .. r0 + lenp of D_{b,k} -> s_d (zero beyond nr and for bad indices).
   auto load_d_chunk = [&](int r0, int lenp) {
-    for (int i = tid; i < MB * (lenp / 2); i += 256) {
-      const int b = i / (lenp / 2), rr = 2 * (i % (lenp / 2));
-      const int s = s_idx[b];
+    constexpr int PAIRS = KCMAX / 2;
+    for (int i = tid; i < MB * PAIRS; i += 256) {
+      const int b = i / PAIRS, rr = 2 * (i % PAIRS);
+      if (rr >= lenp) continue;
+      const long long off = s_drow[b];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (s >= 0 && r0 + rr < a.nr)
-        v = *reinterpret_cast<const float4*>(a.Df + ((size_t)k * a.ns + s) * a.nrp + r0 + rr);
+      if (off >= 0 && r0 + rr < a.nr) v = *reinterpret_cast<const float4*>(a.Df + off + r0 + rr);
       s_d[b * C::DST + rr] = make_float2(v.x, v.y);
       s_d[b * C::DST + rr + 1] = make_float2(v.z, v.w);
     }
@@ -222,15 +227,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     float2 bfr[C::KSW][C::BREG];
     const int ncol_blk = blk0 + (C::S == 1 ? nt_w : 0);
     auto load_b = [&](int r0, int len) {
+      const int rr0 = ks * KSTEP + (C::SPLIT ? lq * 8 : lq);
+      const float2* fb =
+          a.F + (r0 + rr0) * rowstride + ((long long)ncol_blk * a.nf + k) * CB + lr;
+      const bool colok = ncol_blk < a.nvb;
 #pragma unroll
       for (int q = 0; q < C::KSW; ++q) {
-        const int kk = ks + q * C::S;
 #pragma unroll
         for (int e = 0; e < C::BREG; ++e) {
-          const int rr = kk * KSTEP + (C::SPLIT ? lq * 8 + e : lq);
+          const int dr = q * C::S * KSTEP + e;     // row offset from rr0
           float2 v = make_float2(0.f, 0.f);
-          if (rr < len && ncol_blk < a.nvb)
-            v = a.F[(((size_t)(r0 + rr) * a.nvb + ncol_blk) * a.nf + k) * CB + lr];
+          if (colok && rr0 + dr < len) v = fb[dr * rowstride];
           bfr[q][e] = v;
         }
       }
@@ -486,12 +493,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         }
         const int blk = blk0 + nt;
         if (blk < a.nvb) {
+          const int rb = r0 + mt * 16 + lq * 4;
+          float2* fw = a.F + rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = r0 + mt * 16 + lq * 4 + e;
-            if (r < a.nr)
-              a.F[(((size_t)r * a.nvb + blk) * a.nf + k) * CB + lr] = make_float2(re[e], im[e]);
-          }
+          for (int e = 0; e < 4; ++e)
+            if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
         }
       }
     }

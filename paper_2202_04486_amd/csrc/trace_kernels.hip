@@ -69,6 +69,12 @@ struct FftShape {
   static constexpr int NP8 = N2 >= 512 ? 3 : 2;                 // radix-8 passes
   static constexpr int REM = N2 / (NP8 == 3 ? 512 : 64);         // 1, 2 or 4: tail radix
   static constexpr int SC = N2 + N2 / 8;                         // padded scratch per trace
+  // Twiddle table (LDS): [0, N2) exp(-2 pi i k / nt) for the real split; then per
+  // pass the factors laid out [r-1][k] so that lanes read consecutive entries.
+  static constexpr int TW_P1 = N2;                               // W_64^{r k},  k < 8
+  static constexpr int TW_P2 = TW_P1 + 7 * 8;                    // W_512^{r k}, k < 64
+  static constexpr int TW_Q = TW_P2 + (NP8 == 3 ? 7 * 64 : 0);   // W_N2^{q j},  j < 64
+  static constexpr int TW_SIZE = TW_Q + (REM - 1) * 64;
   static_assert(N2 == 64 || N2 == 128 || N2 == 256 || N2 == 512, "unsupported length");
 };
 
@@ -83,10 +89,9 @@ __device__ __forceinline__ void fft_half(float2 (&v)[8], int j, float2* sc, cons
   for (int p = 0; p < S::NP8; ++p) {
     const int Ns = p == 0 ? 1 : (p == 1 ? 8 : 64);
     if (p > 0) {
-      const int k = j & (Ns - 1);
-      const int step = NT / (8 * Ns);
+      const float2* t = tw + (p == 1 ? S::TW_P1 : S::TW_P2) + (j & (Ns - 1));
 #pragma unroll
-      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twid<INV>(tw, r * k * step));
+      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twid<INV>(t, (r - 1) * Ns));
     }
     dft8<INV>(v);
     const bool last = (p == S::NP8 - 1) && (S::REM == 1);
@@ -105,9 +110,9 @@ __device__ __forceinline__ void fft_half(float2 (&v)[8], int j, float2* sc, cons
     for (int h = 0; h < 2; ++h) {
       const int jj = j + L * h;
       float2 x0 = v[h], x1 = v[h + 2], x2 = v[h + 4], x3 = v[h + 6];
-      x1 = cmul(x1, twid<INV>(tw, 2 * jj));
-      x2 = cmul(x2, twid<INV>(tw, 4 * jj));
-      x3 = cmul(x3, twid<INV>(tw, 6 * jj));
+      x1 = cmul(x1, twid<INV>(tw, S::TW_Q + jj));
+      x2 = cmul(x2, twid<INV>(tw, S::TW_Q + 64 + jj));
+      x3 = cmul(x3, twid<INV>(tw, S::TW_Q + 128 + jj));
       const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
       const float2 s13 = cadd(x1, x3), d13 = rot<INV>(csub(x1, x3));
       v[h] = cadd(s02, s13);
@@ -120,7 +125,7 @@ __device__ __forceinline__ void fft_half(float2 (&v)[8], int j, float2* sc, cons
     for (int h = 0; h < 4; ++h) {
       const int jj = j + L * h;
       const float2 x0 = v[h];
-      const float2 x1 = cmul(v[h + 4], twid<INV>(tw, 2 * jj));
+      const float2 x1 = cmul(v[h + 4], twid<INV>(tw, S::TW_Q + jj));
       v[h] = cadd(x0, x1);
       v[h + 4] = csub(x0, x1);
     }
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
   constexpr bool UPDATE = MODE == TM_SGD || MODE == TM_ADAM || MODE == TM_NSGD;
   extern __shared__ float2 smem[];
   float2* s_tw = smem;
-  float2* s_sc = smem + NT;
+  float2* s_sc = smem + S::TW_SIZE;
   float2* s_spec = s_sc + NW * TPW * S::SC;
   __shared__ double s_red[NW];
 
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
   };
   load_state(0);  // requested before the spectral tile is staged
 
-  for (int i = tid; i < NT; i += NTH) s_tw[i] = a.tw[i];
+  for (int i = tid; i < S::TW_SIZE; i += NTH) s_tw[i] = a.tw[i];
   if (MODE != TM_RFFT) {
     for (int i = tid; i < nf * (CB / 2); i += NTH) {
       const int k = i / (CB / 2), c2 = 2 * (i % (CB / 2));
@@ -432,19 +437,38 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
   }
 }
 
+// Builds the twiddle table of FftShape for nt (float64 angles, rounded once).
 __global__ void k_twiddles(float2* tw, int nt) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < nt) {
-    double s, c;
-    sincospi(-2.0 * (double)m / (double)nt, &s, &c);
-    tw[m] = make_float2((float)c, (float)s);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n2 = nt / 2;
+  const int np8 = n2 >= 512 ? 3 : 2;
+  const int rem = n2 / (np8 == 3 ? 512 : 64);
+  const int p1 = n2, p2 = p1 + 56, q0 = p2 + (np8 == 3 ? 448 : 0), total = q0 + (rem - 1) * 64;
+  if (i >= total) return;
+  double num, den;  // angle = -2 pi num / den
+  if (i < p1) {
+    num = i;
+    den = nt;
+  } else if (i < p2) {
+    num = (double)((i - p1) / 8 + 1) * ((i - p1) % 8);
+    den = 64.0;
+  } else if (i < q0) {
+    num = (double)((i - p2) / 64 + 1) * ((i - p2) % 64);
+    den = 512.0;
+  } else {
+    num = (double)((i - q0) / 64 + 1) * ((i - q0) % 64);
+    den = n2;
   }
+  double s, c;
+  sincospi(-2.0 * num / den, &s, &c);
+  tw[i] = make_float2((float)c, (float)s);
 }
 
 template <int NT>
 size_t trace_smem(int nf) {
   using C = TraceCfg<NT>;
-  return sizeof(float2) * ((size_t)NT + (size_t)C::NWAVES * C::TPW * FftShape<C::N2>::SC +
+  using S = FftShape<C::N2>;
+  return sizeof(float2) * ((size_t)S::TW_SIZE + (size_t)C::NWAVES * C::TPW * S::SC +
                            (size_t)nf * SPS);
 }
 
@@ -475,7 +499,7 @@ hipError_t launch_nt(int mode, const TraceArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s) {
-  hipLaunchKernelGGL(k_twiddles, dim3((nt + 255) / 256), dim3(256), 0, s, tw, nt);
+  hipLaunchKernelGGL(k_twiddles, dim3((2 * nt + 255) / 256), dim3(256), 0, s, tw, nt);
   return hipGetLastError();
 }
 
