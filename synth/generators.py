@@ -227,3 +227,24 @@ def random_onsets(nr: int, nvs: int, nt: int, seed: int) -> np.ndarray:
     """Mask onsets drawn uniformly from [0, nt/2) per trace (int32), for mask tests
     that need no geometry."""
     return np.random.default_rng(seed).integers(0, nt // 2, size=(nr, nvs)).astype(np.int32)
+
+
+def data_events(wl: Workload, n: int = 6, rng=None) -> dict:
+    """Hyperbolic events standing in for up-going data where it is not produced by
+    the operator (column-sampled checks at sizes the oracle cannot model whole)."""
+    rng = rng or streams(wl.seed)[4]
+    return {"t0": rng.uniform(0.1, 0.9, size=n), "v": rng.uniform(1500.0, 2500.0, size=n),
+            "a": _signed_amplitudes(rng, n)}
+
+
+def cube_on_device(src, rec, wl: Workload, ev: dict, device, rows_per_chunk: int = 0):
+    """event_cube evaluated on a torch device in row chunks, returned as float32."""
+    import torch
+    n = src.shape[0]
+    out = torch.empty((n, rec.shape[0], wl.nt), dtype=torch.float32, device=device)
+    step = rows_per_chunk or max(1, (1 << 26) // (rec.shape[0] * wl.nt))
+    for s0 in range(0, n, step):
+        rows = np.arange(s0, min(n, s0 + step))
+        out[s0:s0 + len(rows)] = event_cube(src, rec, wl.nt, wl.dt, wl.f0, ev, rows=rows,
+                                            xp=torch, device=device, dtype=torch.float32)
+    return out

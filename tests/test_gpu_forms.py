@@ -1,0 +1,136 @@
+"""The two forms beside the plain FP32 step, at their workloads' full sizes.
+
+Differentiation form (301 x 301 x 301, nt 1024, nf 257, batches of 8 / 32 / 64,
+reciprocity (z + z^T)/2 in-graph, random models of seed 1): adjoint
+dot-product test, exact central differences of the quadratic loss, and the
+gradient against the FP64 oracle.
+
+Precision form at the 1600-trace 3D patch (40 x 40 grid at 25 m, nt 512,
+nf 200, batch 64, mask): the mini-batch gradient of the FP32 and the
+BF16 / FP16 split forms on sampled virtual-source columns, against the oracle
+on the same columns (without reciprocity the columns are independent).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import freq, optim
+
+from gpu_helpers import H, T, f32, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def diff301():
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["diff301"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u_clean = freq.mdc(d, f32(p["r_true"]), wl.nf)
+    u = f32(u_clean + synth.scale_noise(u_clean, p["noise"], wl.snr_db))
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, 64)
+    plan.mdd_set_kernel(T(d))
+    plan.mdd_set_data(T(u))
+    z, v, y = synth.random_arrays(1, (wl.nr, wl.nvs, wl.nt), (wl.nr, wl.nvs, wl.nt),
+                                  (64, wl.nvs, wl.nt))
+    return wl, d, u, plan, f32(z), f32(v), f32(y)
+
+
+@pytest.mark.parametrize("nb", [8, 32, 64])
+def test_autograd_gradient_with_reciprocity(diff301, nb):
+    from paper_2202_04486_amd.autograd import mdc, reciprocity
+    wl, d, u, plan, z0, _, _ = diff301
+    idx = optim.batches(synth.epoch_permutations(wl, 1)[0], nb)[0]
+    it = T(idx, torch.int32)
+    z = T(z0).requires_grad_(True)
+    ub = T(u[idx])
+    pred = mdc(reciprocity(z), it, plan)
+    loss = 0.5 * ((pred - ub).double() ** 2).sum()
+    loss.backward()
+    r = optim.reciprocity(z0)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, wl.nf)
+    go = optim.reciprocity(go)                  # C_r is self-adjoint
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    assert relerr(H(z.grad), go) <= 1e-5
+
+
+@pytest.mark.parametrize("nb", [8, 64])
+def test_autograd_dot_product(diff301, nb):
+    from paper_2202_04486_amd.autograd import mdc
+    wl, _, _, plan, x0, _, y0 = diff301
+    idx = T(optim.batches(synth.epoch_permutations(wl, 1)[0], nb)[0], torch.int32)
+    x = T(x0).requires_grad_(True)
+    y = T(y0[:nb])
+    ax = mdc(x, idx, plan)
+    (ax * y).sum().backward()                   # x.grad = A^T y
+    lhs = float((H(ax) * y0[:nb]).sum())
+    rhs = float((x0 * H(x.grad)).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_autograd_central_difference(diff301):
+    """For the quadratic loss the central difference equals <grad, V> for any step h.
+    V is the oracle's gradient direction (scaled to |z|), so the difference is large
+    compared with the float32 rounding of the loss."""
+    from paper_2202_04486_amd.autograd import mdc, reciprocity
+    wl, d, u, plan, z0, _, _ = diff301
+    b = optim.batches(synth.epoch_permutations(wl, 1)[0], 32)[0]
+    idx = T(b, torch.int32)
+    ub = T(u[b])
+
+    def loss_of(zz):
+        return 0.5 * ((mdc(reciprocity(zz), idx, plan) - ub).double() ** 2).sum()
+
+    _, go = freq.batch_loss_grad(d, optim.reciprocity(z0), u, b, wl.nf)
+    v0 = optim.reciprocity(go)
+    v0 = f32(v0 * (np.linalg.norm(z0) / np.linalg.norm(v0)))
+    z = T(z0).requires_grad_(True)
+    loss_of(z).backward()
+    g = H(z.grad)
+    ip = float(np.sum(g * v0))
+    for h in (1e-2, 1.0):
+        with torch.no_grad():
+            lp = loss_of(T(z0 + h * v0)).item()
+            lm = loss_of(T(z0 - h * v0)).item()
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - ip) <= 1e-4 * abs(ip), (h, fd, ip)
+
+
+@pytest.fixture(scope="module")
+def patch3d():
+    wl = synth.WORKLOADS["patch3d"]
+    dev = torch.device("cuda", 0)
+    xs = synth.positions(wl.ns, wl)
+    d = synth.cube_on_device(xs, xs, wl, synth.down_events(wl), dev)
+    r = synth.cube_on_device(xs, xs, wl, synth.reflection_events(wl), dev)
+    u = synth.cube_on_device(xs, xs, wl, synth.data_events(wl), dev)
+    onset = synth.onsets(wl)
+    idx = optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb)[0]
+    cols = np.array([0, 15, 16, 37, 799, 1203, 1584, 1599])
+    d_b = H(d[torch.from_numpy(idx.astype(np.int64)).to(dev)])
+    u_b = H(u[torch.from_numpy(idx.astype(np.int64)).to(dev)][:, cols, :])
+    r_c = H(r[:, cols, :])
+    _, go = freq.batch_loss_grad(d_b, r_c, u_b, np.arange(wl.nb), wl.nf)
+    go = optim.apply_mask(go, onset[:, cols])
+    return wl, d, r, u, onset, idx, cols, go
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16x3", 1e-3)])
+def test_patch3d_gradient_sampled_columns(patch3d, prec, tol):
+    from paper_2202_04486_amd.plan import Plan
+    wl, d, r, u, onset, idx, cols, go = patch3d
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, precision=prec)
+    plan.mdd_set_kernel(d)
+    plan.mdd_set_data(u)
+    plan.mdd_set_mask(T(onset, torch.int32))
+    G, loss, gn = plan.mdd_stoch_grad(r, T(idx, torch.int32))
+    gs = H(G[:, torch.from_numpy(cols).to(G.device), :])
+    e = relerr(gs, go)
+    print(f"patch3d {prec}: sampled-column gradient rel err {e:.3e}")
+    assert e <= tol
+    assert np.isfinite(loss.item()) and np.isfinite(gn.item())
+    del G
+    plan.close()
+    torch.cuda.empty_cache()
