@@ -31,6 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "stochastic MDD grad evals/s + % MFMA roofline, BF16-split vs FP32 at stated err"
+WORKLOAD_TEXT = {
+    "line2d": "line2d: ns=nr=nvs=201 (10 m line), nt=1024 (4 ms), nf=257, batch 16, Adam, "
+              "causality mask, 20 dB noise, stored model spectra",
+    "patch3d": "patch3d: ns=nr=nvs=1600 (40x40 grid at 25 m), nt=512 (4 ms), nf=200, batch 64, "
+               "Adam, causality mask, noise-free, stored model spectra",
+}
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_adam_line2d.md")
@@ -48,19 +54,8 @@ def make_inputs(wl, dev):
     import synth
     g = synth.streams(wl.seed)
     xs, xr, xv = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl), synth.positions(wl.nvs, wl)
-    dev_ev, rev = synth.down_events(wl, g[0]), synth.reflection_events(wl, g[1])
-    d = torch.empty((wl.ns, wl.nr, wl.nt), dtype=torch.float32, device=dev)
-    chunk = max(1, (1 << 26) // (wl.nr * wl.nt))
-    for s0 in range(0, wl.ns, chunk):
-        rows = np.arange(s0, min(wl.ns, s0 + chunk))
-        d[rows[0]:rows[-1] + 1] = synth.event_cube(xs, xr, wl.nt, wl.dt, wl.f0, dev_ev, rows=rows,
-                                                   xp=torch, device=dev, dtype=torch.float32)
-    r_true = torch.empty((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
-    chunk = max(1, (1 << 26) // (wl.nvs * wl.nt))
-    for s0 in range(0, wl.nr, chunk):
-        rows = np.arange(s0, min(wl.nr, s0 + chunk))
-        r_true[rows[0]:rows[-1] + 1] = synth.event_cube(xr, xv, wl.nt, wl.dt, wl.f0, rev, rows=rows,
-                                                        xp=torch, device=dev, dtype=torch.float32)
+    d = synth.cube_on_device(xs, xr, wl, synth.down_events(wl, g[0]), dev)
+    r_true = synth.cube_on_device(xr, xv, wl, synth.reflection_events(wl, g[1]), dev)
     noise = None
     if wl.snr_db is not None:
         noise = torch.from_numpy(g[2].standard_normal((wl.ns, wl.nvs, wl.nt), dtype=np.float32)).to(dev)
@@ -194,8 +189,11 @@ def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=130)
-    ap.add_argument("--warmup", type=int, default=13)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 10 epochs of line2d, 1 epoch of patch3d)")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="line2d", choices=["line2d", "patch3d"],
+                    help="line2d (default, the headline) or the 1600-trace 3D patch")
     ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -211,7 +209,14 @@ def main():
     import torch
 
     import synth
-    wl = synth.WORKLOADS["line2d"]
+    wl = synth.WORKLOADS[args.workload]
+    spe0 = math.ceil(wl.ns / wl.nb)
+    if args.steps is None:
+        args.steps = 10 * spe0 if args.workload == "line2d" else spe0
+    if args.warmup is None:
+        args.warmup = spe0 if args.workload == "line2d" else 5
+    if args.workload != "line2d":
+        args.no_cpu_baseline = True      # the oracle's full gradient at this size takes minutes
     dev = torch.device("cuda", 0)
     log("generating inputs")
     d, r_true, noise, onset = make_inputs(wl, dev)
@@ -220,7 +225,8 @@ def main():
     p0 = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, device=dev)
     p0.mdd_set_kernel(d)
     u = up_going(p0, r_true, noise, wl, dev)
-    del p0
+    del p0, r_true, noise
+    torch.cuda.empty_cache()
     idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + args.steps, dev)
     torch.cuda.synchronize()
     if args.copy_calibration_mib:
@@ -266,13 +272,21 @@ def main():
     dominant = max(cls_ms, key=lambda k: cls_ms[k] * fp["prof"][k][1])
     upd_ms = cls_ms["update"]
     upd_bytes = 24.0 * Mt                      # R, m, v read and written (float32)
-    traffic = stored_traffic()
-    roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
-                "achieved": upd_bytes / (upd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "traffic": traffic, "traffic_unit": "HBM bytes per launch (counters)",
-                "algorithmic_bytes": upd_bytes}
-    roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
+    traffic = stored_traffic() if args.workload == "line2d" else None
     gemm_flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
+    if dominant == "gemm":
+        gm_ms = cls_ms["gemm"]
+        roofline = {"kernel": "gemm (forward product + residual + loss + adjoint product)",
+                    "bound": "mfma", "achieved": gemm_flops / (gm_ms * 1e-3) / 1e12,
+                    "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "traffic": None,
+                    "algorithmic_flops": gemm_flops}
+    else:
+        roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
+                    "achieved": upd_bytes / (upd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (counters)",
+                    "algorithmic_bytes": upd_bytes}
+    roofline["frac"] = roofline["achieved"] / roofline["peak"]
 
     def gemm_roof(form):
         ms = per_launch(res[form]["prof"], "gemm")
@@ -286,13 +300,13 @@ def main():
         "metric": METRIC, "value": value, "unit": "grad evals/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "line2d: ns=nr=nvs=201 (10 m line), nt=1024 (4 ms), nf=257, "
-                               "batch 16, Adam, causality mask, 20 dB noise, stored model spectra",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "global_batch": nb, "seq_len": wl.nt, "parallelism": "none (1 GPU)"},
         "epoch_ms": ms_step * spe,
         "steps_per_epoch": spe,
         "kernel_ms": cls_ms,
         "dominant_kernel": dominant,
+        "workload": args.workload,
         "roofline": roofline,
         "method_roofline_frac": (alg_bytes / HBM_PEAK_GBS / 1e9) / (ms_step * 1e-3),
         "gemm_roofline": {f: gemm_roof(f) for f in forms},
