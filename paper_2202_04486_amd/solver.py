@@ -27,6 +27,16 @@ class Diverged(RuntimeError):
     """The loss became non-finite or grew by more than `blowup` over its first value."""
 
 
+def check_divergence(losses, loss0: float, blowup: float = 1e6) -> None:
+    """Raise Diverged if any loss is non-finite or exceeds blowup * loss0 (the
+    step size is above the stable range, e.g. beyond the Landweber limit)."""
+    losses = np.asarray(losses, dtype=np.float64)
+    if losses.size == 0:
+        return
+    if not np.all(np.isfinite(losses)) or float(np.max(losses)) > blowup * loss0:
+        raise Diverged(f"loss {float(np.max(losses)):.3e} vs first {loss0:.3e}")
+
+
 def batches(perm, nb: int):
     """ceil(ns / nb) consecutive slices of the permutation, each sorted (int32)."""
     perm = np.asarray(perm)
@@ -107,8 +117,7 @@ class StochasticMDD:
             return
         if self.loss0 is None:
             self.loss0 = float(losses[0])
-        if not np.all(np.isfinite(losses)) or float(np.max(losses)) > self.blowup * self.loss0:
-            raise Diverged(f"loss {float(np.max(losses)):.3e} vs first {self.loss0:.3e}")
+        check_divergence(losses, self.loss0, self.blowup)
 
     def state_dict(self):
         st = {"R": self.R.cpu().numpy(), "t": self.t, "epoch": self.epoch, "cursor": self.cursor,

@@ -1,0 +1,107 @@
+"""Host side of the stochastic solver: batch schedule, divergence detection,
+checkpoint / resume."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import optim, stepsize
+from paper_2202_04486_amd import solver
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("ns,nb", [(201, 32), (201, 16), (1600, 64), (301, 8), (32, 8), (7, 7)])
+def test_schedule_matches_oracle(ns, nb):
+    perm = np.random.default_rng(ns * nb).permutation(ns)
+    a = solver.batches(perm, nb)
+    b = optim.batches(perm, nb)
+    assert len(a) == len(b) == -(-ns // nb)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    tab, lens = solver.epoch_index_table(perm, nb)
+    assert tab.shape == (len(a), nb) and lens.sum() == ns
+    for j, x in enumerate(a):
+        np.testing.assert_array_equal(tab[j, :lens[j]], x)
+
+
+def test_paper_steps_per_epoch():
+    with open(os.path.join(GOLDEN, "schedule_obc.json")) as f:
+        g = json.load(f)
+    assert len(solver.batches(np.arange(g["ns"]), g["nb"])) == g["steps_per_epoch"]
+
+
+def test_divergence_detector_on_landweber_example():
+    """The Landweber iteration of the paper's example diverges at 2.05 / sigma^2 and
+    converges at 1.9 / sigma^2 (Appendix B): the detector trips only on the first."""
+    with open(os.path.join(GOLDEN, "landweber_example.json")) as f:
+        g = json.load(f)
+    a = np.array(g["A"], dtype=float)
+    y = a @ np.array(g["x"], dtype=float)
+    s2 = stepsize.sigma_max2_matrix(a)
+    _, bad = stepsize.landweber(a, y, g["alpha_factor_diverges"] / s2, 2000)
+    _, good = stepsize.landweber(a, y, g["alpha_factor_converges"] / s2, 2000)
+    with pytest.raises(solver.Diverged):
+        solver.check_divergence(np.square(bad), bad[0] ** 2)
+    solver.check_divergence(np.square(good), good[0] ** 2)
+    with pytest.raises(solver.Diverged):
+        solver.check_divergence([1.0, float("nan")], 1.0)
+
+
+@pytest.mark.gpu
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    import torch
+
+    from gpu_helpers import T, f32
+    from oracle import freq
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["tiny2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u = f32(freq.mdc(d, f32(p["r_true"]), wl.nf))
+
+    def make():  # spectra recomputed each step, so a resumed run repeats every operation
+        plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb)
+        plan.mdd_set_kernel(T(d))
+        plan.mdd_set_data(T(u))
+        return solver.StochasticMDD(plan, optimizer="adam", lr=1e-2)
+
+    perms = synth.epoch_permutations(wl, 3)
+    ref = make()
+    for pm in perms:
+        ref.run_epoch(pm)
+    a = make()
+    a.run_epoch(perms[0])
+    a.run_epoch(perms[1], max_steps=2)        # interrupted mid-epoch
+    path = os.path.join(tmp_path, "ckpt.npz")
+    a.save(path)
+    b = make()
+    b.load(path)
+    b.run_epoch(perms[1])                     # finishes the interrupted epoch
+    b.run_epoch(perms[2])
+    assert torch.equal(b.R, ref.R) and torch.equal(b.s0, ref.s0) and torch.equal(b.s1, ref.s1)
+    assert b.t == ref.t and b.epoch == ref.epoch == 3
+
+
+@pytest.mark.gpu
+def test_divergence_detected_on_gpu():
+    from gpu_helpers import T, f32
+    from oracle import freq
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["tiny2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u = f32(freq.mdc(d, f32(p["r_true"]), wl.nf))
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.ns)
+    plan.mdd_set_kernel(T(d))
+    plan.mdd_set_data(T(u))
+    s = solver.StochasticMDD(plan, optimizer="sgd", nb=wl.ns)
+    lr = s.step_size_from_kernel(kappa=0.5, iters=300)
+    s2, _ = stepsize.sigma_max2_kernel(d, wl.nf)
+    assert abs(lr - 1.0 / s2) <= 1e-4 * lr
+    s.lr = 3.0 / s2                           # beyond the Landweber limit 2 / sigma^2
+    with pytest.raises(solver.Diverged):
+        for pm in synth.epoch_permutations(wl, 40):
+            s.run_epoch(pm)
