@@ -504,6 +504,171 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   }
 }
 
+// Persistent, software-pipelined form of the fused product for float32, at most
+// 16 batch rows and at most PIPE_KC receivers (one chunk).  Each workgroup walks a
+// contiguous range of (frequency, column group) items: while one item's products
+// run, the next item's R_k fragments and data entries are already in flight, and
+// D_{b,k} stays in LDS for as long as the frequency does not change.
+constexpr int PIPE_KC = 224;
+constexpr int PIPE_WGS = 512;   // 2 workgroups on each of the 256 CUs (its register use)
+
+__global__ __launch_bounds__(256) void k_gemm_pipe(GemmArgs a) {
+  constexpr int MB = 16, NW = 16, DST = PIPE_KC + 2, RST = NW + 1;
+  constexpr int KSW = PIPE_KC / 4 / 4;        // k-steps per wave (4 waves split K)
+  constexpr int PAIRS = PIPE_KC / 2;          // float4 pairs per D row
+  constexpr int DPT = MB * PAIRS / 256;       // D float4 per thread
+  __shared__ float2 s_d[MB * DST];
+  __shared__ float2 s_part[4 * MB * NW];
+  __shared__ float2 s_res[MB * RST];
+  __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];
+  __shared__ double s_red[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int nvb = a.nvb, total = a.nf * nvb;
+  const int G = gridDim.x;
+  const int rid = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int start = (int)((long long)rid * total / G), end = (int)((long long)(rid + 1) * total / G);
+  if (start >= end) return;
+  const long long rowstride = (long long)nvb * a.nf * CB;
+  const int lenp = (a.nr + 31) & ~31;
+
+  if (tid < MB) {
+    int s = -1;
+    if (tid < a.nb) {
+      s = a.idx[tid];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[tid] = s;
+    s_drow[tid] = s >= 0 ? (long long)s * a.nrp : -1;   // row offset within one frequency
+  }
+  __syncthreads();
+
+  // this thread's residual entry
+  const int urow = tid / NW, ucol = tid % NW;
+  // R_k / G_k of column group cg live at F + (cg * nf + k) * CB (uniform) plus a
+  // 32-bit per-lane offset r * rowstride + lane column.
+  const unsigned rs32 = (unsigned)rowstride;
+  const unsigned lane_off = (unsigned)(wave * 4 + lq) * rs32 + lr;
+  auto load_b = [&](float2 (&dst)[KSW], int k, int cg) {
+    const float2* base = a.F + ((long long)cg * a.nf + k) * CB;
+#pragma unroll
+    for (int q = 0; q < KSW; ++q) {
+      const int rr = wave * 4 + lq + q * 16;
+      dst[q] = rr < a.nr ? base[lane_off + (unsigned)q * 16u * rs32] : make_float2(0.f, 0.f);
+    }
+  };
+  auto load_u = [&](int k, int cg) -> float2 {
+    const int vs = cg * CB + ucol;
+    if (urow < a.nb && vs < a.nvs && s_idx[urow] >= 0)
+      return a.Uf[((size_t)k * a.ns + s_idx[urow]) * a.nvsp + vs];
+    return make_float2(0.f, 0.f);
+  };
+  auto stage_d = [&](int k) {   // D_{b,k} rows -> LDS
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int i = tid + 256 * q;
+      const int b = i / PAIRS, rr = 2 * (i % PAIRS);
+      const long long off = s_drow[b];
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (off >= 0 && rr < a.nr)
+        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.ns * a.nrp + off + rr);
+      s_d[b * DST + rr] = make_float2(v.x, v.y);
+      s_d[b * DST + rr + 1] = make_float2(v.z, v.w);
+    }
+  };
+
+  int cur = start;
+  int k = cur / nvb, cg = cur % nvb;
+  float2 bfr[KSW], bnx[KSW];
+  load_b(bfr, k, cg);
+  float2 up = load_u(k, cg);
+  stage_d(k);
+  __syncthreads();
+
+  while (true) {
+    const int nxt = cur + 1;
+    const bool has_next = nxt < end;
+    int kn = k, cgn = cg;
+    float2 upn = make_float2(0.f, 0.f);
+    if (has_next) {  // next item's operands, in flight during this item's products
+      kn = nxt / nvb;
+      cgn = nxt % nvb;
+      load_b(bnx, kn, cgn);
+      upn = load_u(kn, cgn);
+    }
+
+    // forward: Res = D_b R_k (split over the 4 waves), then the residual and the loss
+    floatx4 ar = floatx4{0.f, 0.f, 0.f, 0.f}, ai = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < KSW; ++q) {
+      const int kk = wave + 4 * q;
+      if (kk * 4 < lenp) {
+        const float2 rv = bfr[q];
+        const float2 dv = s_d[lr * DST + kk * 4 + lq];
+        ar = mfma4(dv.x, rv.x, ar);
+        ar = mfma4(-dv.y, rv.y, ar);
+        ai = mfma4(dv.x, rv.y, ai);
+        ai = mfma4(dv.y, rv.x, ai);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      s_part[(wave * MB + lq * 4 + e) * NW + lr] = make_float2(ar[e], ai[e]);
+    __syncthreads();
+    double lpart = 0.0;
+    {
+      float2 z = s_part[urow * NW + ucol];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) z = cadd(z, s_part[(w * MB + urow) * NW + ucol]);
+      const int vs = cg * CB + ucol;
+      const bool ok = urow < a.nb && vs < a.nvs && s_idx[urow] >= 0;
+      if (ok) {
+        z = csub(z, up);
+        const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
+        lpart = wk * ((double)z.x * z.x + (double)z.y * z.y);
+      } else {
+        z = make_float2(0.f, 0.f);
+      }
+      s_res[urow * RST + ucol] = z;
+    }
+    const double tot = block_sum256(lpart, s_red);   // its barriers also publish s_res
+    if (tid == 0) a.loss_part[cur] = tot;
+    __syncthreads();
+
+    // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
+    for (int mt = wave; mt * 16 < a.nr; mt += 4) {
+      floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < MB / 4; ++kk) {
+        const float2 dv = s_d[(kk * 4 + lq) * DST + mt * 16 + lr];
+        const float2 sv = s_res[(kk * 4 + lq) * RST + lr];
+        re = mfma4(dv.x, sv.x, re);
+        re = mfma4(dv.y, sv.y, re);
+        im = mfma4(dv.x, sv.y, im);
+        im = mfma4(-dv.y, sv.x, im);
+      }
+      const int rb = mt * 16 + lq * 4;
+      float2* base = a.F + ((long long)cg * a.nf + k) * CB;
+      const unsigned o = (unsigned)rb * rs32 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (rb + e < a.nr) base[o + (unsigned)e * rs32] = make_float2(re[e], im[e]);
+    }
+    if (!has_next) break;
+    __syncthreads();  // every wave is done with s_d, s_part, s_res of this item
+    if (kn != k) stage_d(kn);   // new frequency (rare within one workgroup's range)
+#pragma unroll
+    for (int q = 0; q < KSW; ++q) bfr[q] = bnx[q];
+    up = upn;
+    cur = nxt;
+    k = kn;
+    cg = cgn;
+    __syncthreads();
+  }
+}
+
 template <int PREC, int NBT, int TNB>
 hipError_t launch_cfg(int kind, const GemmArgs& a, hipStream_t s) {
   using C = GemmCfg<PREC, NBT, TNB>;
@@ -537,6 +702,15 @@ hipError_t launch_cfg(int kind, const GemmArgs& a, hipStream_t s) {
 
 template <int PREC>
 hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
+  if constexpr (PREC == MDD_PREC_FP32) {
+    if (kind == GK_FUSED && a.nb <= 16 && a.nr <= PIPE_KC) {
+      const int total = a.nf * a.nvb;
+      int grid = total < PIPE_WGS ? total : PIPE_WGS;
+      if (grid >= 8) grid -= grid % 8;
+      hipLaunchKernelGGL(k_gemm_pipe, dim3(grid), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (a.nb <= 16) return launch_cfg<PREC, 1, 1>(kind, a, s);
   if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
   return launch_cfg<PREC, 4, 4>(kind, a, s);
