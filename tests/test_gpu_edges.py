@@ -1,0 +1,92 @@
+"""Edge cases of the GPU path: split-precision operators, a single virtual source,
+mask removal, stored-spectra invalidation, rejected optimiser parameters."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import freq, optim
+
+from gpu_helpers import H, T, batch, make_plan, random_case, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-3), ("fp16x3", 1e-3), ("fp32", 1e-5)])
+@pytest.mark.parametrize("nb", [7, 30, 64])
+def test_operators_all_precisions(prec, tol, nb):
+    ns, nr, nvs, nt, nf = 70, 90, 45, 512, 200
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + 31)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, precision=prec)
+    idx = batch(ns, nb, seed=nb)
+    ug = plan.mdc_forward(T(r), T(idx, torch.int32))
+    assert relerr(H(ug), freq.mdc(d[idx], r, nf)) <= tol
+    gg = plan.mdc_adjoint(T(u[idx]), T(idx, torch.int32))
+    assert relerr(H(gg), freq.mdc_adjoint(d[idx], u[idx], nf)) <= tol
+    G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= tol
+    assert abs(loss.item() - lo) <= tol * lo
+
+
+def test_single_virtual_source():
+    """One virtual source (matrix-vector products per frequency)."""
+    ns, nr, nvs, nt, nf = 40, 37, 1, 1024, 257
+    d, u, r = random_case(ns, nr, nvs, nt, seed=41)
+    plan = make_plan(d, u, nb_max=16, nf=nf)
+    idx = batch(ns, 16, seed=3)
+    G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= 1e-5
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+
+
+def test_mask_can_be_removed():
+    ns, nr, nvs, nt, nf = 20, 18, 19, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=43)
+    onset = synth.random_onsets(nr, nvs, nt, seed=2)
+    plan = make_plan(d, u, onset=onset, nb_max=8, nf=nf)
+    idx = batch(ns, 8, seed=4)
+    G1, _, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    _, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G1), optim.apply_mask(go, onset)) <= 1e-5
+    plan.mdd_set_mask(None)
+    G2, _, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    assert relerr(H(G2), go) <= 1e-5
+
+
+def test_invalidate_after_external_change():
+    """With stored spectra, changing R outside mdd_step needs the invalidation call;
+    after it the step equals one on a fresh plan."""
+    ns, nr, nvs, nt, nf, nb = 24, 20, 21, 256, 129, 8
+    d, u, r0 = random_case(ns, nr, nvs, nt, seed=47)
+    idx = T(batch(ns, nb, seed=5), torch.int32)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, store_rf=True)
+    R = T(r0)
+    plan.mdd_step(R, idx, opt="sgd", lr=1e-4)
+    R.copy_(T(r0 * 0.5))                    # changed behind the library's back
+    plan.mdd_invalidate_model_spectra()
+    plan.mdd_step(R, idx, opt="sgd", lr=1e-4)
+    fresh = make_plan(d, u, nb_max=nb, nf=nf)
+    R2 = T(r0 * 0.5)
+    fresh.mdd_step(R2, idx, opt="sgd", lr=1e-4)
+    assert relerr(H(R), H(R2)) <= 1e-6
+
+
+@pytest.mark.parametrize("kw", [dict(opt="adam", beta1=1.0), dict(opt="adam", eps=0.0),
+                                dict(opt="adam", t=0), dict(opt="nsgd", mu=1.5),
+                                dict(opt="sgd", lr=-1.0), dict(opt="adam", s1=None)])
+def test_bad_optimiser_parameters_rejected(kw):
+    from paper_2202_04486_amd import MddError
+    ns, nr, nvs, nt, nf = 10, 8, 8, 128, 65
+    d, u, r0 = random_case(ns, nr, nvs, nt, seed=53)
+    plan = make_plan(d, u, nb_max=4, nf=nf)
+    R = T(r0)
+    st = {"s0": torch.zeros_like(R), "s1": torch.zeros_like(R)}
+    st.update({k: v for k, v in kw.items() if k in ("s0", "s1")})
+    args = {k: v for k, v in kw.items() if k not in ("s0", "s1")}
+    before = R.clone()
+    with pytest.raises(MddError):
+        plan.mdd_step(R, T(np.arange(4, dtype=np.int32), torch.int32), s0=st["s0"], s1=st["s1"], **args)
+    torch.cuda.synchronize()
+    assert torch.equal(R, before)           # nothing was enqueued
