@@ -712,8 +712,12 @@ hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
     }
   }
   if (a.nb <= 16) return launch_cfg<PREC, 1, 1>(kind, a, s);
-  if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
-  return launch_cfg<PREC, 4, 4>(kind, a, s);
+  if constexpr (PREC == MDD_PREC_BF16X3 || PREC == MDD_PREC_FP16X3) {
+    return launch_gemm_split(kind, PREC, a, s);  // operands split once, in LDS
+  } else {
+    if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
+    return launch_cfg<PREC, 4, 4>(kind, a, s);
+  }
 }
 
 }  // namespace

@@ -1,0 +1,497 @@
+// Split-precision per-frequency products for batches of 17..64 sources.
+//
+// Same operation as the float32 kernels (Theory section, matrix form of the
+// MDC operator per frequency): the forward product D_{b,k} R_k with the
+// residual, float64 loss partials and the adjoint D_{b,k}^H Res_k written over
+// R_k; or the forward / adjoint product alone.  Every complex operand is split
+// into hi + lo halves of bf16 or fp16 and the three significant products
+// hi*hi + hi*lo + lo*hi are accumulated in float32 on
+// v_mfma_f32_16x16x32_{bf16,f16}.
+//
+// The split happens once per element, while staging into LDS, into four
+// planes (re hi, re lo, im hi, im lo) laid out so that each MFMA operand is a
+// single 16-byte LDS read: D_{b,k} as [b][r] for the forward product, its
+// conjugate as [r][b] for the adjoint (the two are never live together, so
+// they share LDS), and the residual as [column][b].  R_k, the right operand of
+// the forward product, goes from HBM to registers and is split there by the
+// one wave that uses it.  fp16 carries a power-of-two scale per receiver chunk
+// and per residual block so that the low halves stay normal.
+#include <type_traits>
+
+#include "device_common.h"
+#include "mdd_internal.h"
+
+namespace mdd {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+struct SplitT {
+  static constexpr bool F16 = PREC == MDD_PREC_FP16X3;
+  using E = std::conditional_t<F16, _Float16, __bf16>;
+  using V = std::conditional_t<F16, halfx8, bf16x8>;
+  using V2 = std::conditional_t<F16, halfx2, bf16x2>;
+  static __device__ __forceinline__ floatx4 mma(V a, V b, floatx4 c) {
+    if constexpr (F16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void split(float x, E& hi, E& lo) {
+    hi = (E)x;
+    lo = (E)(x - (float)hi);
+  }
+};
+
+// acc += A * B, complex operands given as (re hi, re lo, im hi, im lo).
+template <int PREC, typename V>
+__device__ __forceinline__ void cmma3(const V& arh, const V& arl, const V& aih, const V& ail,
+                                      const V& brh, const V& brl, const V& bih, const V& bil,
+                                      floatx4& re, floatx4& im) {
+  using T = SplitT<PREC>;
+  const V naih = -aih, nail = -ail;
+  re = T::mma(arh, brh, re);
+  re = T::mma(arh, brl, re);
+  re = T::mma(arl, brh, re);
+  re = T::mma(naih, bih, re);
+  re = T::mma(naih, bil, re);
+  re = T::mma(nail, bih, re);
+  im = T::mma(arh, bih, im);
+  im = T::mma(arh, bil, im);
+  im = T::mma(arl, bih, im);
+  im = T::mma(aih, brh, im);
+  im = T::mma(aih, brl, im);
+  im = T::mma(ail, brh, im);
+}
+
+// Power-of-two scale bringing max |x| to [2^13, 2^14), and its inverse; the
+// exponent is clamped so that both stay finite.
+__device__ __forceinline__ float2 pow2_scale_pair(float amax) {
+  if (!(amax > 0.f) || !(amax < 3.0e38f)) return make_float2(1.f, 1.f);
+  int e;
+  frexpf(amax, &e);  // amax = m 2^e, m in [0.5, 1)
+  const int sh = min(max(14 - e, -120), 120);
+  return make_float2(ldexpf(1.f, sh), ldexpf(1.f, -sh));
+}
+
+template <int NBT, int TNB>
+struct SCfg {
+  static constexpr int MB = NBT * 16;        // batch rows (32 or 64)
+  static constexpr int NW = TNB * 16;        // columns per workgroup
+  static constexpr int TPWV = NBT * TNB / 4; // forward 16x16 tiles per wave, one column tile
+  static constexpr int MT_STEP = 4 / TNB;    // row-tile stride between a wave's tiles
+  static constexpr int KCMAX = 64;         // receiver chunk
+  static constexpr int KSW = KCMAX / 32;     // forward k-steps per chunk
+  static constexpr int RP = KCMAX + 8;       // forward D plane row pitch (elements)
+  static constexpr int BP = MB + 8;          // adjoint D / residual plane row pitch
+  static constexpr int DF = 4 * MB * RP;     // elements
+  static constexpr int DA = 4 * KCMAX * BP;
+  static constexpr int DSZ = DF > DA ? DF : DA;
+  static constexpr int RS = 4 * NW * BP;
+  static constexpr int FPT = MB * (KCMAX / 2) / 256;      // forward: float4 D loads per thread
+  static constexpr int APT = (MB / 2) * KCMAX / 256;       // adjoint: (b, b+1) pairs per thread
+  static constexpr size_t SMEM = 2 * ((size_t)DSZ + RS);
+  static_assert(NBT * TNB >= 4 && 4 % TNB == 0, "one column tile per wave");
+  static_assert(FPT * 256 == MB * (KCMAX / 2) && APT * 256 == (MB / 2) * KCMAX, "staging");
+};
+
+template <int PREC, int NBT, int TNB, int KIND>
+__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
+  using C = SCfg<NBT, TNB>;
+  using T = SplitT<PREC>;
+  using E = typename T::E;
+  using V = typename T::V;
+  using V2 = typename T::V2;
+  constexpr int MB = C::MB, NW = C::NW, KCMAX = C::KCMAX;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  E* s_dpl = reinterpret_cast<E*>(smem_raw);  // D planes (forward or adjoint layout)
+  E* s_rpl = s_dpl + C::DSZ;                   // residual planes [4][NW][BP]
+  __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];
+  __shared__ double s_red[4];
+  __shared__ float s_max[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ncg = (a.nvb + TNB - 1) / TNB;
+  const int total = a.nf * ncg;
+  const int bid = blockIdx.x;
+  const int full = (total / 8) * 8;
+  // consecutive items (same frequency, neighbouring columns) on one XCD
+  const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
+  const int k = logical / ncg, cg = logical % ncg;
+  const int blk0 = cg * TNB;
+  const long long rowstride = (long long)a.nvb * a.nf * CB;
+  const int nt_w = wave % TNB;  // forward: this wave's column tile
+  const int mt0 = wave / TNB;   // forward: first row tile
+
+  for (int b = tid; b < MB; b += 256) {
+    int s = -1;
+    if (b < a.nb) {
+      s = a.idx[b];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[b] = s;
+    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+  }
+  __syncthreads();
+
+  auto block_max = [&](float m) -> float {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    __syncthreads();
+    if (lane == 0) s_max[wave] = m;
+    __syncthreads();
+    return fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+  };
+  auto amax4 = [](float4 v) { return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))); };
+  // D_{b,k}[r .. r+1] (zero beyond nr and for rejected indices)
+  auto d_pair = [&](int b, int r) -> float4 {
+    const long long off = s_drow[b];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (off >= 0 && r < a.nr) {
+      v = *reinterpret_cast<const float4*>(a.Df + off + r);
+      if (r + 1 >= a.nr) v.z = v.w = 0.f;
+    }
+    return v;
+  };
+  auto dfw = [&](int p, int b, int r) -> E* { return s_dpl + (p * MB + b) * C::RP + r; };
+  auto dad = [&](int p, int r, int b) -> E* { return s_dpl + (p * KCMAX + r) * C::BP + b; };
+  auto rsp = [&](int p, int col, int b) -> E* { return s_rpl + (p * NW + col) * C::BP + b; };
+  auto put2 = [&](E* dhi, float x0, float x1, E* dlo) {
+    E h0, l0, h1, l1;
+    T::split(x0, h0, l0);
+    T::split(x1, h1, l1);
+    V2 hv, lv;
+    hv[0] = h0;
+    hv[1] = h1;
+    lv[0] = l0;
+    lv[1] = l1;
+    *reinterpret_cast<V2*>(dhi) = hv;
+    *reinterpret_cast<V2*>(dlo) = lv;
+  };
+  auto put1 = [&](E* dhi, E* dlo, float x) {
+    E h, l;
+    T::split(x, h, l);
+    *dhi = h;
+    *dlo = l;
+  };
+
+  float ss = 1.f, iss = 1.f;  // residual / batch-spectra scale (fp16) and its inverse
+
+  // ------------------------------------------------------------ forward
+  if constexpr (KIND != GK_ADJ) {
+    floatx4 acc_re[C::TPWV], acc_im[C::TPWV];
+#pragma unroll
+    for (int t = 0; t < C::TPWV; ++t) {
+      acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int ncol = blk0 + nt_w;
+    const float2* fb = a.F + (long long)(lq * 8) * rowstride + ((long long)ncol * a.nf + k) * CB + lr;
+    // R_k rows r0 + q*32 + lq*8 + e of this wave's column tile (zero beyond nr)
+    auto load_r = [&](float2 (&v)[C::KSW][8], int r0) {
+#pragma unroll
+      for (int q = 0; q < C::KSW; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          v[q][e] = make_float2(0.f, 0.f);
+          if (r0 + q * 32 + lq * 8 + e < a.nr && ncol < a.nvb)
+            v[q][e] = fb[(long long)(r0 + q * 32 + e) * rowstride];
+        }
+    };
+    auto load_dfwd = [&](float4 (&v)[C::FPT], int r0) {
+#pragma unroll
+      for (int q = 0; q < C::FPT; ++q) {
+        const int i = tid + 256 * q;
+        v[q] = d_pair(i / (KCMAX / 2), r0 + 2 * (i % (KCMAX / 2)));
+      }
+    };
+    // Software pipeline: the next chunk's R_k fragments (from HBM) are in
+    // flight while the current chunk's products run; D rows come from L2 at
+    // the top of each chunk (prefetching them too costs the registers of a
+    // second wave per SIMD, which loses more than it gains).
+    float2 bnx[C::KSW][8];
+    float4 dv[C::FPT];
+    load_r(bnx, 0);
+#pragma unroll 1
+    for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
+      const int len = min(KCMAX, a.nr - r0);
+      load_dfwd(dv, r0);
+      float2 bfr[C::KSW][8];
+#pragma unroll
+      for (int q = 0; q < C::KSW; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bfr[q][e] = bnx[q][e];
+      float2 sd = make_float2(1.f, 1.f), sr = make_float2(1.f, 1.f);
+      if constexpr (T::F16) {
+        float bm = 0.f, dm = 0.f;
+#pragma unroll
+        for (int q = 0; q < C::KSW; ++q)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bm = fmaxf(bm, fmaxf(fabsf(bfr[q][e].x), fabsf(bfr[q][e].y)));
+#pragma unroll
+        for (int q = 0; q < C::FPT; ++q) dm = fmaxf(dm, amax4(dv[q]));
+        sd = pow2_scale_pair(block_max(dm));
+        sr = pow2_scale_pair(block_max(bm));
+      }
+      __syncthreads();  // the previous chunk's planes are no longer read
+#pragma unroll
+      for (int q = 0; q < C::FPT; ++q) {
+        const int i = tid + 256 * q;
+        const int b = i / (KCMAX / 2), rr = 2 * (i % (KCMAX / 2));
+        put2(dfw(0, b, rr), dv[q].x * sd.x, dv[q].z * sd.x, dfw(1, b, rr));
+        put2(dfw(2, b, rr), dv[q].y * sd.x, dv[q].w * sd.x, dfw(3, b, rr));
+      }
+      __syncthreads();
+      if (r0 + KCMAX < a.nr) {
+        load_r(bnx, r0 + KCMAX);
+      }
+      floatx4 cre[C::TPWV], cim[C::TPWV];
+#pragma unroll
+      for (int t = 0; t < C::TPWV; ++t) {
+        if constexpr (T::F16) {
+          cre[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          cim[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        } else {  // bf16 carries no scale: accumulate in place
+          cre[t] = acc_re[t];
+          cim[t] = acc_im[t];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < C::KSW; ++q) {
+        if (q * 32 < len) {
+          V brh, brl, bih, bil;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            E h, l;
+            T::split(bfr[q][e].x * sr.x, h, l);
+            brh[e] = h;
+            brl[e] = l;
+            T::split(bfr[q][e].y * sr.x, h, l);
+            bih[e] = h;
+            bil[e] = l;
+          }
+#pragma unroll
+          for (int t = 0; t < C::TPWV; ++t) {
+            const int row = (mt0 + t * C::MT_STEP) * 16 + lr;
+            const int col = q * 32 + lq * 8;
+            const V arh = *reinterpret_cast<const V*>(dfw(0, row, col));
+            const V arl = *reinterpret_cast<const V*>(dfw(1, row, col));
+            const V aih = *reinterpret_cast<const V*>(dfw(2, row, col));
+            const V ail = *reinterpret_cast<const V*>(dfw(3, row, col));
+            cmma3<PREC>(arh, arl, aih, ail, brh, brl, bih, bil, cre[t], cim[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < C::TPWV; ++t) {
+        if constexpr (T::F16) {
+          acc_re[t] += (cre[t] * sd.y) * sr.y;
+          acc_im[t] += (cim[t] * sd.y) * sr.y;
+        } else {
+          acc_re[t] = cre[t];
+          acc_im[t] = cim[t];
+        }
+      }
+    }
+
+    // Residual (GK_FUSED) or predicted batch spectra (GK_FWD).
+    double lpart = 0.0;
+    float rm = 0.f;
+    float2 zr[C::TPWV][4];
+#pragma unroll
+    for (int t = 0; t < C::TPWV; ++t) {
+      const int mt = mt0 + t * C::MT_STEP;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = mt * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+        const int vs = blk0 * CB + col;
+        const bool ok = row < a.nb && vs < a.nvs && s_idx[row] >= 0;
+        float2 z = make_float2(acc_re[t][e], acc_im[t][e]);
+        if constexpr (KIND == GK_FUSED) {
+          if (ok) {
+            z = csub(z, a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs]);
+            lpart += (k == 0 || 2 * k == a.nt ? 1.0 : 2.0) * ((double)z.x * z.x + (double)z.y * z.y);
+          } else {
+            z = make_float2(0.f, 0.f);
+          }
+          zr[t][e] = z;
+          rm = fmaxf(rm, fmaxf(fabsf(z.x), fabsf(z.y)));
+        } else {
+          if (row < a.nb && blk0 + nt_w < a.nvb)
+            a.Bsp[(((size_t)row * a.nvb + blk0 + nt_w) * a.nf + k) * CB + lr] =
+                ok ? z : make_float2(0.f, 0.f);
+        }
+      }
+    }
+    if constexpr (KIND == GK_FWD) return;
+    const double tot = block_sum256(lpart, s_red);
+    if (tid == 0) a.loss_part[logical] = tot;
+    if constexpr (T::F16) {
+      const float2 sc = pow2_scale_pair(block_max(rm));
+      ss = sc.x;
+      iss = sc.y;
+    }
+#pragma unroll
+    for (int t = 0; t < C::TPWV; ++t) {
+      const int mt = mt0 + t * C::MT_STEP;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = mt * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+        put1(rsp(0, col, row), rsp(1, col, row), zr[t][e].x * ss);
+        put1(rsp(2, col, row), rsp(3, col, row), zr[t][e].y * ss);
+      }
+    }
+  } else {
+    // Adjoint alone: the batch spectra V_k are the right operand.
+    auto bsp = [&](int i) -> float2 {
+      const int row = i / NW, col = i % NW;
+      const int blk = blk0 + col / 16;
+      if (row < a.nb && blk < a.nvb && s_idx[row] >= 0)
+        return a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)];
+      return make_float2(0.f, 0.f);
+    };
+    if constexpr (T::F16) {
+      float m = 0.f;
+      for (int i = tid; i < MB * NW; i += 256) {
+        const float2 z = bsp(i);
+        m = fmaxf(m, fmaxf(fabsf(z.x), fabsf(z.y)));
+      }
+      const float2 sc = pow2_scale_pair(block_max(m));
+      ss = sc.x;
+      iss = sc.y;
+    }
+    for (int i = tid; i < MB * NW; i += 256) {
+      const float2 z = bsp(i);
+      const int row = i / NW, col = i % NW;
+      put1(rsp(0, col, row), rsp(1, col, row), z.x * ss);
+      put1(rsp(2, col, row), rsp(3, col, row), z.y * ss);
+    }
+  }
+
+  // ------------------------------------------------------------ adjoint
+  // G_k[r][c] = sum_b conj(D[b][r]) Res[b][c]; each wave owns row tiles
+  // wave, wave + 4, ... of the chunk and all TNB column tiles.  D is staged
+  // as (b, b+1) pairs of one receiver per lane, four lanes per receiver, so
+  // that a wave's LDS stores fall in distinct banks; the next chunk's D rows
+  // are in flight during the current chunk's products.
+  float2 dj[C::APT][2];
+  auto load_dadj = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < C::APT; ++q) {
+      const int u = tid + 256 * q;
+      const int r = r0 + ((u >> 2) % KCMAX), b = 2 * ((u & 3) + 4 * (u / (4 * KCMAX)));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const long long off = s_drow[b + h];
+        dj[q][h] = (off >= 0 && r < a.nr) ? a.Df[off + r] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  load_dadj(0);
+#pragma unroll 1
+  for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
+    const int len = min(KCMAX, a.nr - r0);
+    float2 sd = make_float2(1.f, 1.f);
+    if constexpr (T::F16) {
+      float dm = 0.f;
+#pragma unroll
+      for (int q = 0; q < C::APT; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) dm = fmaxf(dm, fmaxf(fabsf(dj[q][h].x), fabsf(dj[q][h].y)));
+      sd = pow2_scale_pair(block_max(dm));
+    }
+    __syncthreads();  // residual planes complete; previous D planes no longer read
+#pragma unroll
+    for (int q = 0; q < C::APT; ++q) {
+      const int u = tid + 256 * q;
+      const int rr = (u >> 2) % KCMAX, b = 2 * ((u & 3) + 4 * (u / (4 * KCMAX)));
+      put2(dad(0, rr, b), dj[q][0].x * sd.x, dj[q][1].x * sd.x, dad(1, rr, b));
+      put2(dad(2, rr, b), -dj[q][0].y * sd.x, -dj[q][1].y * sd.x, dad(3, rr, b));  // conj
+    }
+    __syncthreads();
+    if (r0 + KCMAX < a.nr) load_dadj(r0 + KCMAX);
+    for (int mt = wave; mt * 16 < len; mt += 4) {
+      V arh[MB / 32], arl[MB / 32], aih[MB / 32], ail[MB / 32];
+#pragma unroll
+      for (int kk = 0; kk < MB / 32; ++kk) {
+        const int r = mt * 16 + lr, b = kk * 32 + lq * 8;
+        arh[kk] = *reinterpret_cast<const V*>(dad(0, r, b));
+        arl[kk] = *reinterpret_cast<const V*>(dad(1, r, b));
+        aih[kk] = *reinterpret_cast<const V*>(dad(2, r, b));
+        ail[kk] = *reinterpret_cast<const V*>(dad(3, r, b));
+      }
+#pragma unroll
+      for (int nt = 0; nt < TNB; ++nt) {
+        floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < MB / 32; ++kk) {
+          const int b = kk * 32 + lq * 8, col = nt * 16 + lr;
+          const V brh = *reinterpret_cast<const V*>(rsp(0, col, b));
+          const V brl = *reinterpret_cast<const V*>(rsp(1, col, b));
+          const V bih = *reinterpret_cast<const V*>(rsp(2, col, b));
+          const V bil = *reinterpret_cast<const V*>(rsp(3, col, b));
+          cmma3<PREC>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im);
+        }
+        if constexpr (T::F16) {
+          re = (re * sd.y) * iss;
+          im = (im * sd.y) * iss;
+        }
+        const int blk = blk0 + nt;
+        if (blk < a.nvb) {
+          const int rb = r0 + mt * 16 + lq * 4;
+          float2* fw = a.F + rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, int NBT, int TNB, int KIND>
+hipError_t launch_one(const GemmArgs& a, hipStream_t s) {
+  using C = SCfg<NBT, TNB>;
+  const int ncg = (a.nvb + TNB - 1) / TNB;
+  auto kern = &k_gemm_split<PREC, NBT, TNB, KIND>;
+  if (C::SMEM > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::SMEM);
+  hipLaunchKernelGGL(kern, dim3(a.nf * ncg), dim3(256), C::SMEM, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int NBT, int TNB>
+hipError_t launch_split_cfg(int kind, const GemmArgs& a, hipStream_t s) {
+  switch (kind) {
+    case GK_FUSED: return launch_one<PREC, NBT, TNB, GK_FUSED>(a, s);
+    case GK_FWD: return launch_one<PREC, NBT, TNB, GK_FWD>(a, s);
+    case GK_ADJ: return launch_one<PREC, NBT, TNB, GK_ADJ>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC>
+hipError_t launch_split_prec(int kind, const GemmArgs& a, hipStream_t s) {
+  if (a.nb <= 32) return launch_split_cfg<PREC, 2, 2>(kind, a, s);
+  return launch_split_cfg<PREC, 4, 4>(kind, a, s);
+}
+
+}  // namespace
+
+// Split forms (bf16x3, fp16x3) for 16 < nb <= 64.
+hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s) {
+  if (a.nb <= 16 || a.nb > NB_LIMIT) return hipErrorInvalidValue;
+  switch (precision) {
+    case MDD_PREC_BF16X3: return launch_split_prec<MDD_PREC_BF16X3>(kind, a, s);
+    case MDD_PREC_FP16X3: return launch_split_prec<MDD_PREC_FP16X3>(kind, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mdd

@@ -80,6 +80,8 @@ struct GemmArgs {
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s);
 hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s);
 hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s);
+// bf16x3 / fp16x3 products for 16 < nb <= NB_LIMIT (gemm_split.hip)
+hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
                           hipStream_t s);
