@@ -39,8 +39,8 @@ WORKLOAD_TEXT = {
 }
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_adam_line2d.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_04486_amd", "csrc", "trace_kernels.hip")
+TRAFFIC_FILE = {w: os.path.join(ROOT, "profiles", f"traffic_{w}.md") for w in WORKLOAD_TEXT}
+CSRC = os.path.join(ROOT, "paper_2202_04486_amd", "csrc")
 
 
 def log(msg):
@@ -132,20 +132,23 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per launch of the update kernel from the committed counter summary,
-    or None if it is missing or the kernel source changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def stored_traffic(workload, key):
+    """HBM bytes per launch of kernel `key` ("update", "gemm_fp32", "gemm_bf16x3", ...) from
+    the committed counter summary of the workload, or None if it is missing or the kernel's
+    source file changed since the counters were taken."""
+    path = TRAFFIC_FILE.get(workload)
+    if not path or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, _, v = line.strip()[2:].partition(":")
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != source_hash(KERNEL_SOURCE):
+    src = vals.get(f"{key}_source")
+    if not src or vals.get(f"{key}_source_sha256") != source_hash(os.path.join(CSRC, src)):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[f"{key}_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -272,13 +275,15 @@ def main():
     dominant = max(cls_ms, key=lambda k: cls_ms[k] * fp["prof"][k][1])
     upd_ms = cls_ms["update"]
     upd_bytes = 24.0 * Mt                      # R, m, v read and written (float32)
-    traffic = stored_traffic() if args.workload == "line2d" else None
+    traffic = stored_traffic(args.workload, "update")
     gemm_flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
     if dominant == "gemm":
         gm_ms = cls_ms["gemm"]
         roofline = {"kernel": "gemm (forward product + residual + loss + adjoint product)",
                     "bound": "mfma", "achieved": gemm_flops / (gm_ms * 1e-3) / 1e12,
-                    "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "traffic": None,
+                    "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                    "traffic": stored_traffic(args.workload, "gemm_fp32"),
+                    "traffic_unit": "HBM bytes per launch (counters)",
                     "algorithmic_flops": gemm_flops}
     else:
         roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
@@ -291,9 +296,11 @@ def main():
     def gemm_roof(form):
         ms = per_launch(res[form]["prof"], "gemm")
         hw = gemm_flops * (3 if form in ("bf16x3", "fp16x3") else 1)
+        tr = stored_traffic(args.workload, f"gemm_{form}")
         return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
                 "mfma_tflops": hw / (ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS[form],
-                "frac": hw / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[form]}
+                "frac": hw / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[form],
+                "traffic": tr, "hbm_gbs": (tr / (ms * 1e-3) / 1e9) if tr else None}
 
     alg_bytes = 24.0 * Mt + 2 * 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * wl.nvs * wl.nf
     out = {

@@ -90,3 +90,27 @@ def test_bad_optimiser_parameters_rejected(kw):
         plan.mdd_step(R, T(np.arange(4, dtype=np.int32), torch.int32), s0=st["s0"], s1=st["s1"], **args)
     torch.cuda.synchronize()
     assert torch.equal(R, before)           # nothing was enqueued
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("nb", [17, 32, 33, 63])
+def test_split_batches_with_bad_and_repeated_indices(prec, nb):
+    """Split-precision products at the batch-size boundaries of their tilings (17..32 and
+    33..64 rows), receivers not a multiple of the 64-receiver chunk, columns not a multiple
+    of the column group, a repeated index (counted twice) and two rejected indices (zero
+    wavefields), with the causality mask."""
+    ns, nr, nvs, nt, nf = 80, 131, 70, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + 61)
+    onset = synth.onsets(synth.WORKLOADS["tiny2d"].replace(dt=0.002), nr, nvs)
+    plan = make_plan(d, u, onset=onset, nb_max=nb, nf=nf, precision=prec)
+    good = batch(ns, nb - 3, seed=nb)
+    idx = np.concatenate([good, [good[0], -1, ns]]).astype(np.int32)
+    G, loss, gn = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    used = np.concatenate([good, [good[0]]])
+    lo, go = freq.batch_loss_grad(d, r, u, used, nf)
+    go = optim.apply_mask(go, onset)
+    assert relerr(H(G), go) <= 1e-3
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    assert abs(gn.item() - float(np.sum(go * go))) <= 2e-3 * float(np.sum(go * go))
+    G2, loss2, gn2 = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    assert torch.equal(G, G2) and torch.equal(loss, loss2) and torch.equal(gn, gn2)
