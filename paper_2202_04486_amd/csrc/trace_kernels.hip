@@ -19,6 +19,21 @@ namespace {
 
 constexpr int SPS = CB + 1;  // LDS row stride of a spectral tile (odd -> no bank aliasing)
 
+// Streaming access to the model and optimiser state: each element is read and
+// written once per step and the whole state is larger than the last-level
+// cache, so these accesses are marked non-temporal.  That keeps the spectra
+// (written here, read by the next step's products, and the reverse) resident
+// in the cache.
+typedef float stream2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 stream_load(const float2* p) {
+  const stream2 v = __builtin_nontemporal_load(reinterpret_cast<const stream2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stream_store(float2 x, float2* p) {
+  const stream2 v = {x.x, x.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<stream2*>(p));
+}
+
 template <bool INV>
 __device__ __forceinline__ float2 rot(float2 a) {  // * -i (forward) or * +i (inverse)
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
@@ -218,9 +233,9 @@ __device__ __forceinline__ double tile_sum(double v, double* red) {
 }
 
 // One workgroup per tile of CB traces, one wavefront per trace (or several
-// traces per wavefront for short traces).  Update modes issue the loads of the
-// model and optimiser state before the spectral tile is staged, so their
-// latency overlaps the staging and the inverse transform.
+// traces per wavefront for short traces).  Update modes load a trace's model
+// and optimiser state right after its inverse transform and store them right
+// after the update, so that each element's read and write are close in time.
 template <int NT, int MODE>
 __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
   using C = TraceCfg<NT>;
@@ -252,13 +267,12 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
       const float2* M1 = reinterpret_cast<const float2*>(a.st1 + trace * NT);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        rv[r] = valid ? R[j + L * r] : make_float2(0.f, 0.f);
-        if constexpr (MODE != TM_SGD) m0[r] = valid ? M0[j + L * r] : make_float2(0.f, 0.f);
-        if constexpr (MODE == TM_ADAM) m1[r] = valid ? M1[j + L * r] : make_float2(0.f, 0.f);
+        rv[r] = valid ? stream_load(R + j + L * r) : make_float2(0.f, 0.f);
+        if constexpr (MODE != TM_SGD) m0[r] = valid ? stream_load(M0 + j + L * r) : make_float2(0.f, 0.f);
+        if constexpr (MODE == TM_ADAM) m1[r] = valid ? stream_load(M1 + j + L * r) : make_float2(0.f, 0.f);
       }
     }
   };
-  load_state(0);  // requested before the spectral tile is staged
 
   for (int i = tid; i < S::TW_SIZE; i += NTH) s_tw[i] = a.tw[i];
   if (MODE != TM_RFFT) {
@@ -289,9 +303,9 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
       for (int r = 0; r < 8; ++r) {
         float2 z = make_float2(0.f, 0.f);
         if (valid) {
-          z = x[j + L * r];
+          z = stream_load(x + j + L * r);
           if (a.x_in2) {
-            const float2 y = x2[j + L * r];
+            const float2 y = stream_load(x2 + j + L * r);
             z.x += a.mu2 * y.x;
             z.y += a.mu2 * y.y;
           }
@@ -318,6 +332,7 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
     } else {
       irfft_merge<NT>(v, j, s_spec, c, nf, s_tw);
       fft_half<NT, true>(v, j, sc, s_tw);
+      load_state(it);  // read just before its update, written back soon after
       const float inv_n2 = 1.0f / float(N2);
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = cscale(v[r], inv_n2);  // time samples 2n, 2n+1
@@ -401,9 +416,9 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
             float2* M1 = reinterpret_cast<float2*>(a.st1 + trace * NT);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-              R[j + L * r] = rv[r];
-              if constexpr (MODE != TM_SGD) M0[j + L * r] = m0[r];
-              if constexpr (MODE == TM_ADAM) M1[j + L * r] = m1[r];
+              stream_store(rv[r], R + j + L * r);
+              if constexpr (MODE != TM_SGD) stream_store(m0[r], M0 + j + L * r);
+              if constexpr (MODE == TM_ADAM) stream_store(m1[r], M1 + j + L * r);
             }
           }
           if (a.store_spec) {  // spectra of the next evaluation point, over this column
@@ -417,7 +432,6 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
             }
             if (j == 0 && nf > N2) s_spec[N2 * SPS + c] = xn;
           }
-          if (it + 1 < C::ITERS) load_state(it + 1);
         }
       }
     }
