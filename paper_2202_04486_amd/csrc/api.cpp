@@ -41,7 +41,7 @@ Layout make_layout(const mdd_dims& d) {
   L.f = take(c8 * d.nr * nvb * d.nf * CB);
   L.bsp = take(c8 * d.nb_max * nvb * d.nf * CB);
   L.lossp = take(sizeof(double) * d.nf * nvb);
-  L.gnp = take(sizeof(double) * d.nr * nvb);
+  L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
   L.total = o;
   return L;
 }
@@ -174,7 +174,7 @@ struct mdd_plan {
     r.nb = nb;
     r.ns = d.ns;
     r.gn_part = gnp();
-    r.n_gn = d.nr * nvb;
+    r.n_gn = d.nr * nvb * trace_update_split(d.nt);
     r.loss_out = loss_out;
     r.gnorm2_out = gnorm2_out;
     return run(MDD_KC_REDUCE, [&] { return launch_reduce(r, stream); });

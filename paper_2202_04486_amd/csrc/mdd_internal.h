@@ -79,6 +79,9 @@ struct GemmArgs {
 
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s);
 hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s);
+// Workgroups per 16-column block in the gradient / update modes at this nt; each
+// writes one float64 partial, so those launches write rows * ncb * split partials.
+int trace_update_split(int nt);
 hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s);
 // bf16x3 / fp16x3 products for 16 < nb <= NB_LIMIT (gemm_split.hip)
 hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s);

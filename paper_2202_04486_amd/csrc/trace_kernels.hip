@@ -17,7 +17,6 @@
 namespace mdd {
 namespace {
 
-constexpr int SPS = CB + 1;  // LDS row stride of a spectral tile (odd -> no bank aliasing)
 
 // Streaming access to the model and optimiser state: each element is read and
 // written once per step and the whole state is larger than the last-level
@@ -183,7 +182,7 @@ __device__ __forceinline__ void rfft_split(float2 (&v)[8], int j, int lane, cons
 
 // Inverse of rfft_split: from the one-sided spectrum column c of a staged tile
 // (bins >= nf are zero) build Z[k] = E[k] + i O[k] for k = j + L r.
-template <int NT>
+template <int NT, int SPS>
 __device__ __forceinline__ void irfft_merge(float2 (&v)[8], int j, const float2* spec, int c,
                                             int nf, const float2* tw) {
   constexpr int N2 = NT / 2;
@@ -205,17 +204,25 @@ __device__ __forceinline__ void irfft_merge(float2 (&v)[8], int j, const float2*
   }
 }
 
-template <int NT>
+template <int NT, int MODE>
 struct TraceCfg {
   static constexpr int N2 = NT / 2;
   static constexpr int L = FftShape<N2>::L;
   static constexpr int TPW = 64 / L;              // traces per wavefront at a time
-  // One tile of CB traces per workgroup.  At nt = 1024 eight wavefronts take two
-  // traces each in turn, which keeps the workgroup at <= 80 KB of LDS so that two
-  // workgroups share a CU and one's arithmetic overlaps the other's memory traffic.
-  static constexpr int NWAVES = NT == 1024 ? 8 : CB / TPW;
-  static constexpr int ITERS = CB / (NWAVES * TPW);
+  // The gradient and update modes of long traces give each workgroup half of a
+  // 16-column spectral block (CW = 8 traces, four wavefronts): three such
+  // workgroups fit a CU where one full-block workgroup of eight wavefronts did
+  // (registers and LDS), and the grid's last partial round is half as long.
+  // The two halves of a block run on the same XCD, so its L2 serves both.
+  static constexpr bool UPD = MODE == TM_GRAD || MODE == TM_SGD || MODE == TM_ADAM ||
+                              MODE == TM_NSGD;
+  static constexpr int SPLIT = (UPD && NT >= 512) ? 2 : 1;
+  static constexpr int CW = CB / SPLIT;           // columns (traces) per workgroup
+  static constexpr int NWAVES = NT == 1024 ? 8 / SPLIT : CW / TPW;
+  static constexpr int ITERS = CW / (NWAVES * TPW);
   static constexpr int THREADS = 64 * NWAVES;
+  static constexpr int SPS = CW + 1;              // LDS row stride of the spectral tile (odd)
+  static_assert(ITERS * NWAVES * TPW == CW, "tile");
 };
 
 // Deterministic sum over the workgroup of one double per thread (result in thread 0).
@@ -237,9 +244,10 @@ __device__ __forceinline__ double tile_sum(double v, double* red) {
 // and optimiser state right after its inverse transform and store them right
 // after the update, so that each element's read and write are close in time.
 template <int NT, int MODE>
-__global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
-  using C = TraceCfg<NT>;
+__global__ __launch_bounds__((TraceCfg<NT, MODE>::THREADS)) void k_trace(TraceArgs a) {
+  using C = TraceCfg<NT, MODE>;
   constexpr int N2 = C::N2, L = C::L, TPW = C::TPW, NW = C::NWAVES, NTH = C::THREADS;
+  constexpr int CW = C::CW, SPS = C::SPS;
   using S = FftShape<N2>;
   constexpr bool UPDATE = MODE == TM_SGD || MODE == TM_ADAM || MODE == TM_NSGD;
   extern __shared__ float2 smem[];
@@ -250,16 +258,25 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = lane / L, j = lane % L;
-  const int row = blockIdx.x / a.ncb, cb = blockIdx.x % a.ncb;
+  // workgroup -> (tile, half): groups of 16 consecutive ids hold both halves of
+  // 8 tiles, ids g and g + 8 (same XCD under round-robin dispatch) one tile.
+  int tile = blockIdx.x, half = 0;
+  if constexpr (C::SPLIT == 2) {
+    const int g = blockIdx.x / 16, w = blockIdx.x % 16;
+    const int m = min(8, a.rows * a.ncb - 8 * g);  // tiles in this group
+    tile = 8 * g + w % m;
+    half = w / m;
+  }
+  const int row = tile / a.ncb, cb = tile % a.ncb;
   const int nf = a.nf;
-  float2* gspec = a.spec + row * a.s_row + cb * a.s_cb;
-  auto column = [&](int it) { return it * NW * TPW + wave * TPW + p; };  // trace within the tile
+  float2* gspec = a.spec + row * a.s_row + cb * a.s_cb + half * CW;
+  auto column = [&](int it) { return it * NW * TPW + wave * TPW + p; };  // trace within the half
 
   // Model / optimiser state of the lane's trace in iteration `it`.
   float2 rv[8], m0[8], m1[8];
   auto load_state = [&](int it) {
     if constexpr (UPDATE) {
-      const int col = cb * CB + column(it);
+      const int col = cb * CB + half * CW + column(it);
       const bool valid = col < a.ncols;
       const long long trace = (long long)row * a.ncols + col;
       const float2* R = reinterpret_cast<const float2*>(a.model + trace * NT);
@@ -276,8 +293,8 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
 
   for (int i = tid; i < S::TW_SIZE; i += NTH) s_tw[i] = a.tw[i];
   if (MODE != TM_RFFT) {
-    for (int i = tid; i < nf * (CB / 2); i += NTH) {
-      const int k = i / (CB / 2), c2 = 2 * (i % (CB / 2));
+    for (int i = tid; i < nf * (CW / 2); i += NTH) {
+      const int k = i / (CW / 2), c2 = 2 * (i % (CW / 2));
       const float4 z = *reinterpret_cast<const float4*>(gspec + k * a.s_k + c2);
       s_spec[k * SPS + c2] = make_float2(z.x, z.y);
       s_spec[k * SPS + c2 + 1] = make_float2(z.z, z.w);
@@ -291,7 +308,7 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
 #pragma unroll 1
   for (int it = 0; it < C::ITERS; ++it) {
     const int c = column(it);
-    const int col = cb * CB + c;
+    const int col = cb * CB + half * CW + c;
     const bool valid = col < a.ncols;
     const long long trace = (long long)row * a.ncols + col;
     float2 v[8];
@@ -330,7 +347,7 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
         if (j == 0 && nf <= N2) part += (double)xn.x * xn.x;
       }
     } else {
-      irfft_merge<NT>(v, j, s_spec, c, nf, s_tw);
+      irfft_merge<NT, SPS>(v, j, s_spec, c, nf, s_tw);
       fft_half<NT, true>(v, j, sc, s_tw);
       load_state(it);  // read just before its update, written back soon after
       const float inv_n2 = 1.0f / float(N2);
@@ -443,8 +460,8 @@ __global__ __launch_bounds__(TraceCfg<NT>::THREADS) void k_trace(TraceArgs a) {
   }
   if (MODE == TM_RFFT || (UPDATE && a.store_spec)) {
     __syncthreads();
-    for (int i = tid; i < nf * (CB / 2); i += NTH) {
-      const int k = i / (CB / 2), c2 = 2 * (i % (CB / 2));
+    for (int i = tid; i < nf * (CW / 2); i += NTH) {
+      const int k = i / (CW / 2), c2 = 2 * (i % (CW / 2));
       const float2 z0 = s_spec[k * SPS + c2], z1 = s_spec[k * SPS + c2 + 1];
       *reinterpret_cast<float4*>(gspec + k * a.s_k + c2) = make_float4(z0.x, z0.y, z1.x, z1.y);
     }
@@ -478,18 +495,19 @@ __global__ void k_twiddles(float2* tw, int nt) {
   tw[i] = make_float2((float)c, (float)s);
 }
 
-template <int NT>
+template <int NT, int MODE>
 size_t trace_smem(int nf) {
-  using C = TraceCfg<NT>;
+  using C = TraceCfg<NT, MODE>;
   using S = FftShape<C::N2>;
   return sizeof(float2) * ((size_t)S::TW_SIZE + (size_t)C::NWAVES * C::TPW * S::SC +
-                           (size_t)nf * SPS);
+                           (size_t)nf * C::SPS);
 }
 
 template <int NT, int MODE>
 hipError_t launch_mode(const TraceArgs& a, hipStream_t s) {
-  const dim3 grid(a.rows * a.ncb), block(TraceCfg<NT>::THREADS);
-  const size_t sm = trace_smem<NT>(a.nf);
+  using C = TraceCfg<NT, MODE>;
+  const dim3 grid(a.rows * a.ncb * C::SPLIT), block(C::THREADS);
+  const size_t sm = trace_smem<NT, MODE>(a.nf);
   if (sm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trace<NT, MODE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -515,6 +533,16 @@ hipError_t launch_nt(int mode, const TraceArgs& a, hipStream_t s) {
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s) {
   hipLaunchKernelGGL(k_twiddles, dim3((2 * nt + 255) / 256), dim3(256), 0, s, tw, nt);
   return hipGetLastError();
+}
+
+int trace_update_split(int nt) {
+  switch (nt) {
+    case 128: return TraceCfg<128, TM_ADAM>::SPLIT;
+    case 256: return TraceCfg<256, TM_ADAM>::SPLIT;
+    case 512: return TraceCfg<512, TM_ADAM>::SPLIT;
+    case 1024: return TraceCfg<1024, TM_ADAM>::SPLIT;
+    default: return 1;
+  }
 }
 
 hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s) {
