@@ -711,9 +711,13 @@ hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
       return hipGetLastError();
     }
   }
+  if constexpr (PREC == MDD_PREC_BF16X3 || PREC == MDD_PREC_FP16X3) {
+    if (a.nb > 16 || (kind == GK_FUSED && a.nr <= SPLIT_PIPE_KC))
+      return launch_gemm_split(kind, PREC, a, s);  // operands split once, in LDS
+  }
   if (a.nb <= 16) return launch_cfg<PREC, 1, 1>(kind, a, s);
   if constexpr (PREC == MDD_PREC_BF16X3 || PREC == MDD_PREC_FP16X3) {
-    return launch_gemm_split(kind, PREC, a, s);  // operands split once, in LDS
+    return hipErrorInvalidValue;  // not reached: nb > 16 went to launch_gemm_split
   } else {
     if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
     return launch_cfg<PREC, 4, 4>(kind, a, s);

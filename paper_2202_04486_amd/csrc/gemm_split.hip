@@ -46,12 +46,30 @@ struct SplitT {
   }
 };
 
-// acc += A * B, complex operands given as (re hi, re lo, im hi, im lo).
-template <int PREC, typename V>
+// The 16x16x16 shape (four k values per lane), for products over at most 16
+// batch rows.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+struct SplitK16 {
+  static constexpr bool F16 = PREC == MDD_PREC_FP16X3;
+  using V = std::conditional_t<F16, halfx4, bf16x4>;
+  static __device__ __forceinline__ floatx4 mma(V a, V b, floatx4 c) {
+    if constexpr (F16) return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(shortx4, a),
+                                                       __builtin_bit_cast(shortx4, b), c, 0, 0, 0);
+  }
+};
+
+// acc += A * B, complex operands given as (re hi, re lo, im hi, im lo); T
+// supplies the MFMA shape.
+template <typename T, typename V>
 __device__ __forceinline__ void cmma3(const V& arh, const V& arl, const V& aih, const V& ail,
                                       const V& brh, const V& brl, const V& bih, const V& bil,
                                       floatx4& re, floatx4& im) {
-  using T = SplitT<PREC>;
   const V naih = -aih, nail = -ail;
   re = T::mma(arh, brh, re);
   re = T::mma(arh, brl, re);
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
             const V arl = *reinterpret_cast<const V*>(dfw(1, row, col));
             const V aih = *reinterpret_cast<const V*>(dfw(2, row, col));
             const V ail = *reinterpret_cast<const V*>(dfw(3, row, col));
-            cmma3<PREC>(arh, arl, aih, ail, brh, brl, bih, bil, cre[t], cim[t]);
+            cmma3<T>(arh, arl, aih, ail, brh, brl, bih, bil, cre[t], cim[t]);
           }
         }
       }
@@ -435,7 +453,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
           const V brl = *reinterpret_cast<const V*>(rsp(1, col, b));
           const V bih = *reinterpret_cast<const V*>(rsp(2, col, b));
           const V bil = *reinterpret_cast<const V*>(rsp(3, col, b));
-          cmma3<PREC>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im);
+          cmma3<T>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im);
         }
         if constexpr (T::F16) {
           re = (re * sd.y) * iss;
@@ -451,6 +469,273 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batches of at most 16 sources over at most SPLIT_PIPE_KC receivers, fused
+// kind: a persistent kernel.  Each workgroup walks a contiguous range of
+// (frequency, 16-column block) items.  D_{b,k} is split into LDS planes
+// [b][r] once per frequency; the next item's R_k fragments and U entries are
+// in flight during the current item's products.  Forward: 16x16x32 products,
+// the receiver steps spread over the four waves and their partial sums added
+// through LDS.  Adjoint: 16x16x16 products over the batch (k = b), each wave
+// owning receiver tiles wave, wave + 4, ...; its A operand (conj D, four
+// batch rows of one receiver per lane) is read from the same [b][r] planes.
+constexpr int SP_WGS = 512;  // persistent workgroups: two per CU (its register use)
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
+  using T = SplitT<PREC>;
+  using S = SplitK16<PREC>;
+  using E = typename T::E;
+  using V = typename T::V;
+  using V2 = typename T::V2;
+  using V4 = typename S::V;
+  constexpr int MB = 16, NW = 16, KC = SPLIT_PIPE_KC;
+  constexpr int RP = KC + 8;          // D plane row pitch (elements)
+  constexpr int RSP = MB + 4;         // residual plane row pitch: [col][b]
+  constexpr int KSW = KC / 32 / 4;    // forward k-steps per wave
+  constexpr int DPT = MB * (KC / 2) / 256;  // D float4 loads per thread
+  __shared__ __align__(16) E s_d[4 * MB * RP];
+  __shared__ __align__(16) E s_r[4 * NW * RSP];
+  __shared__ float2 s_part[4 * MB * NW];
+  __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];
+  __shared__ double s_red[4];
+  __shared__ float s_mx[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int nvb = a.nvb, total = a.nf * nvb;
+  const int G = gridDim.x;
+  const int rid = (G % 8 == 0) ? (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int start = (int)((long long)rid * total / G), end = (int)((long long)(rid + 1) * total / G);
+  if (start >= end) return;
+  const long long rowstride = (long long)nvb * a.nf * CB;
+
+  if (tid < MB) {
+    int s = -1;
+    if (tid < a.nb) {
+      s = a.idx[tid];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[tid] = s;
+    s_drow[tid] = s >= 0 ? (long long)s * a.nrp : -1;  // row offset within one frequency
+  }
+  __syncthreads();
+
+  auto wave_max = [](float m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    return m;
+  };
+  auto dpl = [&](int p, int b, int r) -> E* { return s_d + (p * MB + b) * RP + r; };
+  auto rpl = [&](int p, int col, int b) -> E* { return s_r + (p * NW + col) * RSP + b; };
+
+  // R_k rows (wave + 4 q) * 32 + lq * 8 + e of column block cg, lane column lr
+  auto load_b = [&](float2 (&dst)[KSW][8], int k, int cg) {
+    const float2* base = a.F + ((long long)cg * a.nf + k) * CB + lr;
+#pragma unroll
+    for (int q = 0; q < KSW; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int r = (wave + 4 * q) * 32 + lq * 8 + e;
+        dst[q][e] = r < a.nr ? base[(long long)r * rowstride] : make_float2(0.f, 0.f);
+      }
+  };
+  const int urow = tid / NW, ucol = tid % NW;  // this thread's residual entry
+  auto load_u = [&](int k, int cg) -> float2 {
+    const int vs = cg * CB + ucol;
+    if (urow < a.nb && vs < a.nvs && s_idx[urow] >= 0)
+      return a.Uf[((size_t)k * a.ns + s_idx[urow]) * a.nvsp + vs];
+    return make_float2(0.f, 0.f);
+  };
+  // D_{b,k} -> split planes; returns the (fp16) scale and its inverse
+  auto stage_d = [&](int k) -> float2 {
+    float4 dv[DPT];
+    float m = 0.f;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int i = tid + 256 * q;
+      const int b = i / (KC / 2), rr = 2 * (i % (KC / 2));
+      const long long off = s_drow[b];
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (off >= 0 && rr < a.nr) {
+        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.ns * a.nrp + off + rr);
+        if (rr + 1 >= a.nr) v.z = v.w = 0.f;
+      }
+      dv[q] = v;
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    float2 sd = make_float2(1.f, 1.f);
+    if constexpr (T::F16) {
+      m = wave_max(m);
+      if (lane == 0) s_mx[wave] = m;
+      __syncthreads();
+      sd = pow2_scale_pair(fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
+    }
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int i = tid + 256 * q;
+      const int b = i / (KC / 2), rr = 2 * (i % (KC / 2));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // h = 0: real parts, 1: imaginary parts
+        const float x0 = (h ? dv[q].y : dv[q].x) * sd.x, x1 = (h ? dv[q].w : dv[q].z) * sd.x;
+        E h0, l0, h1, l1;
+        T::split(x0, h0, l0);
+        T::split(x1, h1, l1);
+        V2 hv, lv;
+        hv[0] = h0;
+        hv[1] = h1;
+        lv[0] = l0;
+        lv[1] = l1;
+        *reinterpret_cast<V2*>(dpl(2 * h, b, rr)) = hv;
+        *reinterpret_cast<V2*>(dpl(2 * h + 1, b, rr)) = lv;
+      }
+    }
+    return sd;
+  };
+
+  int cur = start;
+  int k = cur / nvb, cg = cur % nvb;
+  float2 bfr[KSW][8], bnx[KSW][8];
+  load_b(bfr, k, cg);
+  float2 up = load_u(k, cg);
+  float2 sd = stage_d(k);
+  __syncthreads();
+
+  while (true) {
+    const int nxt = cur + 1;
+    const bool has_next = nxt < end;
+    int kn = k, cgn = cg;
+    float2 upn = make_float2(0.f, 0.f);
+    if (has_next) {  // next item's operands, in flight during this item's products
+      kn = nxt / nvb;
+      cgn = nxt % nvb;
+      load_b(bnx, kn, cgn);
+      upn = load_u(kn, cgn);
+    }
+
+    // forward: this wave's receiver steps of D_b R_k
+    float2 sr = make_float2(1.f, 1.f);
+    if constexpr (T::F16) {  // per-wave scale: each wave unscales its own partial sum
+      float m = 0.f;
+#pragma unroll
+      for (int q = 0; q < KSW; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(bfr[q][e].x), fabsf(bfr[q][e].y)));
+      sr = pow2_scale_pair(wave_max(m));
+    }
+    floatx4 ar = floatx4{0.f, 0.f, 0.f, 0.f}, ai = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < KSW; ++q) {
+      const int kq = wave + 4 * q;
+      if (kq * 32 < a.nr) {
+        V brh, brl, bih, bil;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          E h, l;
+          T::split(bfr[q][e].x * sr.x, h, l);
+          brh[e] = h;
+          brl[e] = l;
+          T::split(bfr[q][e].y * sr.x, h, l);
+          bih[e] = h;
+          bil[e] = l;
+        }
+        const int col = kq * 32 + lq * 8;
+        const V arh = *reinterpret_cast<const V*>(dpl(0, lr, col));
+        const V arl = *reinterpret_cast<const V*>(dpl(1, lr, col));
+        const V aih = *reinterpret_cast<const V*>(dpl(2, lr, col));
+        const V ail = *reinterpret_cast<const V*>(dpl(3, lr, col));
+        cmma3<T>(arh, arl, aih, ail, brh, brl, bih, bil, ar, ai);
+      }
+    }
+    if constexpr (T::F16) {
+      ar = (ar * sd.y) * sr.y;
+      ai = (ai * sd.y) * sr.y;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s_part[(wave * MB + lq * 4 + e) * NW + lr] = make_float2(ar[e], ai[e]);
+    __syncthreads();
+
+    // residual, float64 loss partial and (fp16) the residual's block scale
+    double lpart = 0.0;
+    float2 z = s_part[urow * NW + ucol];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) z = cadd(z, s_part[(w * MB + urow) * NW + ucol]);
+    {
+      const int vs = cg * CB + ucol;
+      const bool ok = urow < a.nb && vs < a.nvs && s_idx[urow] >= 0;
+      if (ok) {
+        z = csub(z, up);
+        const double wk = (k == 0 || 2 * k == a.nt) ? 1.0 : 2.0;
+        lpart = wk * ((double)z.x * z.x + (double)z.y * z.y);
+      } else {
+        z = make_float2(0.f, 0.f);
+      }
+    }
+    lpart = wave_sum(lpart);
+    const float zm = wave_max(fmaxf(fabsf(z.x), fabsf(z.y)));
+    if (lane == 0) {
+      s_red[wave] = lpart;
+      s_mx[wave] = zm;
+    }
+    __syncthreads();
+    if (tid == 0) a.loss_part[cur] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+    float2 ss = make_float2(1.f, 1.f);
+    if constexpr (T::F16) ss = pow2_scale_pair(fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
+    {
+      E h, l;
+      T::split(z.x * ss.x, h, l);
+      *rpl(0, ucol, urow) = h;
+      *rpl(1, ucol, urow) = l;
+      T::split(z.y * ss.x, h, l);
+      *rpl(2, ucol, urow) = h;
+      *rpl(3, ucol, urow) = l;
+    }
+    __syncthreads();
+
+    // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
+    float2* gbase = a.F + ((long long)cg * a.nf + k) * CB + lr;
+    V4 brh, brl, bih, bil;  // Res rows lq*4 .. lq*4+3, column lr
+    brh = *reinterpret_cast<const V4*>(rpl(0, lr, lq * 4));
+    brl = *reinterpret_cast<const V4*>(rpl(1, lr, lq * 4));
+    bih = *reinterpret_cast<const V4*>(rpl(2, lr, lq * 4));
+    bil = *reinterpret_cast<const V4*>(rpl(3, lr, lq * 4));
+    for (int mt = wave; mt * 16 < a.nr; mt += 4) {
+      V4 arh, arl, aih, ail;  // conj D: batch rows lq*4 + i, receiver mt*16 + lr
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int b = lq * 4 + i, r = mt * 16 + lr;
+        arh[i] = *dpl(0, b, r);
+        arl[i] = *dpl(1, b, r);
+        aih[i] = -*dpl(2, b, r);
+        ail[i] = -*dpl(3, b, r);
+      }
+      floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+      cmma3<S>(arh, arl, aih, ail, brh, brl, bih, bil, re, im);
+      if constexpr (T::F16) {
+        re = (re * sd.y) * ss.y;
+        im = (im * sd.y) * ss.y;
+      }
+      const int rb = mt * 16 + lq * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (rb + e < a.nr) gbase[(long long)(rb + e) * rowstride] = make_float2(re[e], im[e]);
+    }
+    if (!has_next) break;
+    __syncthreads();  // every wave is done with s_d, s_part, s_r of this item
+    if (kn != k) sd = stage_d(kn);  // new frequency (rare within one workgroup's range)
+#pragma unroll
+    for (int q = 0; q < KSW; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bfr[q][e] = bnx[q][e];
+    up = upn;
+    cur = nxt;
+    k = kn;
+    cg = cgn;
+    __syncthreads();
   }
 }
 
@@ -478,15 +763,24 @@ hipError_t launch_split_cfg(int kind, const GemmArgs& a, hipStream_t s) {
 
 template <int PREC>
 hipError_t launch_split_prec(int kind, const GemmArgs& a, hipStream_t s) {
+  if (a.nb <= 16) {
+    if (kind != GK_FUSED || a.nr > SPLIT_PIPE_KC) return hipErrorInvalidValue;
+    const int total = a.nf * a.nvb;
+    int grid = total < SP_WGS ? total : SP_WGS;
+    if (grid >= 8) grid -= grid % 8;
+    hipLaunchKernelGGL(k_gemm_spipe<PREC>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   if (a.nb <= 32) return launch_split_cfg<PREC, 2, 2>(kind, a, s);
   return launch_split_cfg<PREC, 4, 4>(kind, a, s);
 }
 
 }  // namespace
 
-// Split forms (bf16x3, fp16x3) for 16 < nb <= 64.
+// Split forms (bf16x3, fp16x3): 16 < nb <= 64, or the fused kind at nb <= 16 over at
+// most SPLIT_PIPE_KC receivers.
 hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s) {
-  if (a.nb <= 16 || a.nb > NB_LIMIT) return hipErrorInvalidValue;
+  if (a.nb < 1 || a.nb > NB_LIMIT) return hipErrorInvalidValue;
   switch (precision) {
     case MDD_PREC_BF16X3: return launch_split_prec<MDD_PREC_BF16X3>(kind, a, s);
     case MDD_PREC_FP16X3: return launch_split_prec<MDD_PREC_FP16X3>(kind, a, s);

@@ -83,7 +83,9 @@ hipError_t launch_trace(int mode, const TraceArgs& a, hipStream_t s);
 // writes one float64 partial, so those launches write rows * ncb * split partials.
 int trace_update_split(int nt);
 hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s);
-// bf16x3 / fp16x3 products for 16 < nb <= NB_LIMIT (gemm_split.hip)
+// bf16x3 / fp16x3 products (gemm_split.hip): 16 < nb <= NB_LIMIT, or the fused kind
+// at nb <= 16 over at most SPLIT_PIPE_KC receivers (persistent kernel).
+constexpr int SPLIT_PIPE_KC = 256;
 hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,

@@ -258,11 +258,12 @@ __global__ __launch_bounds__((TraceCfg<NT, MODE>::THREADS)) void k_trace(TraceAr
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = lane / L, j = lane % L;
-  // workgroup -> (tile, half): groups of 16 consecutive ids hold both halves of
-  // 8 tiles, ids g and g + 8 (same XCD under round-robin dispatch) one tile.
+  // workgroup -> (tile, part): a group of 8 * SPLIT consecutive ids holds every
+  // part of 8 tiles, ids w, w + 8, ... (one XCD under round-robin dispatch) the
+  // parts of one tile.
   int tile = blockIdx.x, half = 0;
-  if constexpr (C::SPLIT == 2) {
-    const int g = blockIdx.x / 16, w = blockIdx.x % 16;
+  if constexpr (C::SPLIT > 1) {
+    const int g = blockIdx.x / (8 * C::SPLIT), w = blockIdx.x % (8 * C::SPLIT);
     const int m = min(8, a.rows * a.ncb - 8 * g);  // tiles in this group
     tile = 8 * g + w % m;
     half = w / m;

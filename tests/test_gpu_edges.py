@@ -114,3 +114,27 @@ def test_split_batches_with_bad_and_repeated_indices(prec, nb):
     assert abs(gn.item() - float(np.sum(go * go))) <= 2e-3 * float(np.sum(go * go))
     G2, loss2, gn2 = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
     assert torch.equal(G, G2) and torch.equal(loss, loss2) and torch.equal(gn, gn2)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("nb,nr", [(1, 33), (9, 256), (16, 201), (16, 257)])
+def test_split_small_batches(prec, nb, nr):
+    """Split-precision fused products at batches of at most 16: the persistent kernel up to
+    256 receivers (and the tiled kernel beyond), with a rejected index, the mask and
+    columns that do not fill the last 16-column block."""
+    ns, nvs, nt, nf = 40, 37, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + nr)
+    onset = synth.onsets(synth.WORKLOADS["tiny2d"].replace(dt=0.002), nr, nvs)
+    plan = make_plan(d, u, onset=onset, nb_max=nb, nf=nf, precision=prec)
+    good = batch(ns, nb, seed=nb)
+    idx = good.copy()
+    if nb > 1:
+        idx[-1] = ns + 1          # rejected: a source with zero wavefields
+        good = good[:-1]
+    G, loss, gn = plan.mdd_stoch_grad(T(r), T(idx.astype(np.int32), torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, good, nf)
+    go = optim.apply_mask(go, onset)
+    assert relerr(H(G), go) <= 1e-3
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    G2, loss2, _ = plan.mdd_stoch_grad(T(r), T(idx.astype(np.int32), torch.int32))
+    assert torch.equal(G, G2) and torch.equal(loss, loss2)
