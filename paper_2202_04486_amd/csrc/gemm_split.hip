@@ -739,6 +739,442 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 33..64 batch rows, fused kind: a warp-specialised workgroup of eight waves.
+// Waves 0-3 compute with the same LDS planes and MFMA tiling as the kernel
+// above (each owns one 16-column tile and all four row tiles).  Waves 4-7 only
+// stream R_k: they keep WS_DEPTH 64-receiver chunks in flight in their
+// registers and hand each to the compute waves through a two-slot LDS ring of
+// float32 values.  D_{b,k} chunks are double-buffered as well, so a single
+// barrier separates consecutive chunks.  (With one role per wave, each wave
+// has one chunk in flight and waits on memory for about half of its time.)
+constexpr int WS_DEPTH = 3;
+constexpr int WS_CW = 8;                   // compute waves (two per SIMD)
+constexpr int WS_LW = 4;                   // loader waves
+constexpr int WS_THREADS = 64 * (WS_CW + WS_LW);
+
+template <int PREC>
+__global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
+  using C = SCfg<4, 4>;
+  using T = SplitT<PREC>;
+  using E = typename T::E;
+  using V = typename T::V;
+  using V2 = typename T::V2;
+  constexpr int MB = C::MB, NW = C::NW, KC = C::KCMAX, KSW = C::KSW;
+  constexpr int RRP = NW + 2;                 // ring row pitch (complex values)
+  constexpr int RING = KC * RRP;              // complex values per ring slot
+  constexpr int NCT = 64 * WS_CW, NLT = 64 * WS_LW;  // compute / loader threads
+  constexpr int LPT = KC * NW / 2 / NLT;      // float4 per loader thread per chunk
+  constexpr int TPC = C::TPWV * 4 / WS_CW;    // forward 16x16 tiles per compute wave
+  constexpr int FPT = MB * (KC / 2) / NCT;    // forward D float4 per compute thread
+  static_assert(LPT * NLT == KC * NW / 2 && FPT * NCT == MB * (KC / 2), "split");
+  static_assert(WS_DEPTH == 3, "the loader's register rotation is unrolled by three");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  E* s_dsl = reinterpret_cast<E*>(smem_raw);  // two D slots of C::DSZ elements
+  float2* s_ring = reinterpret_cast<float2*>(smem_raw + 2 * sizeof(E) * C::DSZ);
+  E* s_rpl = reinterpret_cast<E*>(s_ring);    // residual planes; the ring is free by then
+  static_assert(sizeof(E) * C::RS <= sizeof(float2) * 2 * RING, "residual planes fit the ring");
+  __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];
+  __shared__ double s_red[WS_CW];
+  __shared__ float s_dmax[3][WS_CW];  // fp16: per D chunk (mod 3), per compute wave
+  __shared__ float s_rmax[2][WS_LW];  // fp16: per ring slot, per loader wave
+  __shared__ float s_max[WS_CW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool compute = wave < WS_CW;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ncg = (a.nvb + 3) / 4;
+  const int total = a.nf * ncg;
+  const int bid = blockIdx.x, full = (total / 8) * 8;
+  const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
+  const int k = logical / ncg, cg = logical % ncg;
+  const int blk0 = cg * 4;
+  const long long rowstride = (long long)a.nvb * a.nf * CB;
+  const int nc = (a.nr + KC - 1) / KC;
+  const int nt_w = wave & 3;            // compute, forward: column tile
+  const int rt0 = (wave >> 2) * TPC;    // compute, forward: first of its row tiles
+  const int li = tid - NCT;             // loader: thread index within the loaders
+
+  for (int b = tid; b < MB; b += WS_THREADS) {
+    int s = -1;
+    if (b < a.nb) {
+      s = a.idx[b];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[b] = s;
+    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+  }
+  __syncthreads();
+
+  auto wave_max = [](float m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    return m;
+  };
+  auto maxn = [](const float* v, int n) {
+    float m = v[0];
+    for (int i = 1; i < n; ++i) m = fmaxf(m, v[i]);
+    return m;
+  };
+  auto amax4 = [](float4 v) { return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))); };
+  auto dfw = [&](int sl, int p, int b, int r) -> E* { return s_dsl + sl * C::DSZ + (p * MB + b) * C::RP + r; };
+  auto rsp = [&](int p, int col, int b) -> E* { return s_rpl + (p * NW + col) * C::BP + b; };
+  auto put2 = [&](E* dhi, float x0, float x1, E* dlo) {
+    E h0, l0, h1, l1;
+    T::split(x0, h0, l0);
+    T::split(x1, h1, l1);
+    V2 hv, lv;
+    hv[0] = h0;
+    hv[1] = h1;
+    lv[0] = l0;
+    lv[1] = l1;
+    *reinterpret_cast<V2*>(dhi) = hv;
+    *reinterpret_cast<V2*>(dlo) = lv;
+  };
+  auto put1 = [&](E* dhi, E* dlo, float x) {
+    E h, l;
+    T::split(x, h, l);
+    *dhi = h;
+    *dlo = l;
+  };
+  auto scale_of = [&](const float* v, int n) -> float2 {
+    if constexpr (T::F16) return pow2_scale_pair(maxn(v, n));
+    else return make_float2(1.f, 1.f);
+  };
+
+  // ---- loader side: R_k chunk c (rows c*KC ..) of the four column blocks.  The
+  // loads are unconditional (addresses clamped into the array) so that nothing
+  // waits for them before they are written to the ring, where rows beyond nr and
+  // blocks beyond nvb become zeros.
+  auto issue = [&](float4 (&dst)[LPT], int c) {
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int i = li + NLT * q;
+      const int rr = i / (NW / 2), cp = 2 * (i % (NW / 2));
+      const int r = min(c * KC + rr, a.nr - 1), blk = min(blk0 + cp / CB, a.nvb - 1);
+      dst[q] = *reinterpret_cast<const float4*>(a.F + (long long)r * rowstride +
+                                                ((long long)blk * a.nf + k) * CB + cp % CB);
+    }
+  };
+  auto put_ring = [&](const float4 (&src)[LPT], int c) {
+    const int slot = c & 1;
+    float m = 0.f;
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int i = li + NLT * q;
+      const int rr = i / (NW / 2), cp = 2 * (i % (NW / 2));
+      const bool ok = c * KC + rr < a.nr && blk0 + cp / CB < a.nvb;
+      const float4 v = ok ? src[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(s_ring + slot * RING + rr * RRP + cp) = v;
+      m = fmaxf(m, amax4(v));
+    }
+    if constexpr (T::F16) {
+      m = wave_max(m);
+      if (lane == 0) s_rmax[slot][wave - WS_CW] = m;
+    }
+  };
+
+  // ---- compute side: D chunks for the forward product ([b][r] planes)
+  // D loads are unconditional too (a rejected index reads row 0 of the frequency,
+  // a receiver beyond nr reads receiver 0); staging zeroes them.  Only the fp16
+  // form looks at the values when they arrive (its per-chunk scale).
+  const long long drow0 = (long long)k * a.ns * a.nrp;
+  auto d_at = [&](int b, int r) -> long long {
+    const long long off = s_drow[b];
+    return (off >= 0 ? off : drow0) + (r < a.nr ? r : 0);
+  };
+  auto d_ok = [&](int b, int r) { return s_drow[b] >= 0 && r < a.nr; };
+  float4 dv[FPT];
+  auto load_dfwd = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < FPT; ++q) {
+      const int i = tid + NCT * q;
+      dv[q] = *reinterpret_cast<const float4*>(a.Df + d_at(i / (KC / 2), c * KC + 2 * (i % (KC / 2))));
+    }
+    if constexpr (T::F16) {
+      float m = 0.f;
+#pragma unroll
+      for (int q = 0; q < FPT; ++q) {
+        const int i = tid + NCT * q;
+        const int b = i / (KC / 2), r = c * KC + 2 * (i % (KC / 2));
+        if (d_ok(b, r)) m = fmaxf(m, r + 1 < a.nr ? amax4(dv[q]) : fmaxf(fabsf(dv[q].x), fabsf(dv[q].y)));
+      }
+      m = wave_max(m);
+      if (lane == 0) s_dmax[c % 3][wave] = m;
+    }
+  };
+  auto stage_dfwd = [&](int sl, float sd, int c) {
+#pragma unroll
+    for (int q = 0; q < FPT; ++q) {
+      const int i = tid + NCT * q;
+      const int b = i / (KC / 2), rr = 2 * (i % (KC / 2)), r = c * KC + rr;
+      float4 v = d_ok(b, r) ? dv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r + 1 >= a.nr) v.z = v.w = 0.f;
+      put2(dfw(sl, 0, b, rr), v.x * sd, v.z * sd, dfw(sl, 1, b, rr));
+      put2(dfw(sl, 2, b, rr), v.y * sd, v.w * sd, dfw(sl, 3, b, rr));
+    }
+  };
+
+  // The two roles run separate loops with the same barriers (2 + nc of them), so
+  // that the loaders' in-flight registers and the compute waves' accumulators
+  // are not live at the same time in either.
+  floatx4 acc_re[TPC], acc_im[TPC];
+#pragma unroll
+  for (int t = 0; t < TPC; ++t) {
+    acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  if (compute) {
+    // prologue: D chunk 0 staged, chunk 1 in flight
+    load_dfwd(0);
+    __syncthreads();
+    stage_dfwd(0, scale_of(s_dmax[0], WS_CW).x, 0);
+    load_dfwd(1);  // chunks past the end load clamped addresses and stage zeros
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < nc; ++c) {
+      const int sl = c & 1;
+      const int len = min(KC, a.nr - c * KC);
+      const float2 sd = scale_of(s_dmax[c % 3], WS_CW), sr = scale_of(s_rmax[sl], WS_LW);
+      floatx4 cre[TPC], cim[TPC];
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        if constexpr (T::F16) {
+          cre[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          cim[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        } else {
+          cre[t] = acc_re[t];
+          cim[t] = acc_im[t];
+        }
+      }
+      const float2* ring = s_ring + sl * RING + nt_w * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < KSW; ++q) {
+        if (q * 32 < len) {
+          V brh, brl, bih, bil;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float2 x = ring[(q * 32 + lq * 8 + e) * RRP];
+            E h, l;
+            T::split(x.x * sr.x, h, l);
+            brh[e] = h;
+            brl[e] = l;
+            T::split(x.y * sr.x, h, l);
+            bih[e] = h;
+            bil[e] = l;
+          }
+#pragma unroll
+          for (int t = 0; t < TPC; ++t) {
+            const int row = (rt0 + t) * 16 + lr, col = q * 32 + lq * 8;
+            const V arh = *reinterpret_cast<const V*>(dfw(sl, 0, row, col));
+            const V arl = *reinterpret_cast<const V*>(dfw(sl, 1, row, col));
+            const V aih = *reinterpret_cast<const V*>(dfw(sl, 2, row, col));
+            const V ail = *reinterpret_cast<const V*>(dfw(sl, 3, row, col));
+            cmma3<T>(arh, arl, aih, ail, brh, brl, bih, bil, cre[t], cim[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        if constexpr (T::F16) {
+          acc_re[t] += (cre[t] * sd.y) * sr.y;
+          acc_im[t] += (cim[t] * sd.y) * sr.y;
+        } else {
+          acc_re[t] = cre[t];
+          acc_im[t] = cim[t];
+        }
+      }
+      // the next D chunk into the other slot (last read by chunk c - 1); unconditional
+      // so that the loads in flight are the same on every path
+      stage_dfwd(sl ^ 1, scale_of(s_dmax[(c + 1) % 3], WS_CW).x, c + 1);
+      load_dfwd(c + 2);
+      __syncthreads();
+    }
+  } else {
+    // prologue: R chunk 0 in the ring, chunks 1 .. 3 in flight
+    // Every issue is unconditional (chunks past the end read clamped addresses and
+    // are written as zeros) so that the loads in flight are the same on every path
+    // and each ring write waits only for its own chunk.
+    float4 rq[WS_DEPTH][LPT];
+    issue(rq[0], 0);
+    issue(rq[1], 1);
+    issue(rq[2], 2);
+    __syncthreads();
+    put_ring(rq[0], 0);
+    issue(rq[0], 3);
+    __syncthreads();
+    int c0 = 0;
+#pragma unroll 1
+    for (; c0 + WS_DEPTH <= nc; c0 += WS_DEPTH) {
+#pragma unroll
+      for (int u = 0; u < WS_DEPTH; ++u) {  // R chunk c + 1 into the slot chunk c - 1 used
+        const int c = c0 + u;
+        put_ring(rq[(u + 1) % WS_DEPTH], c + 1);
+        issue(rq[(u + 1) % WS_DEPTH], c + 1 + WS_DEPTH);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WS_DEPTH - 1; ++u) {  // the last nc % 3 chunks
+      const int c = c0 + u;
+      if (c < nc) {
+        put_ring(rq[(u + 1) % WS_DEPTH], c + 1);
+        __syncthreads();
+      }
+    }
+  }
+
+  // residual and float64 loss partial (compute waves)
+  double lpart = 0.0;
+  float rm = 0.f;
+  float2 zr[TPC][4];
+  if (compute) {
+    float2 uv[TPC][4];  // all of this lane's U_b entries in flight at once
+#pragma unroll
+    for (int t = 0; t < TPC; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (rt0 + t) * 16 + lq * 4 + e, vs = blk0 * CB + nt_w * 16 + lr;
+        const int s = row < a.nb ? max(s_idx[row], 0) : 0;
+        uv[t][e] = a.Uf[((size_t)k * a.ns + s) * a.nvsp + min(vs, a.nvsp - 1)];
+      }
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (rt0 + t) * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+        const int vs = blk0 * CB + col;
+        float2 z = make_float2(acc_re[t][e], acc_im[t][e]);
+        if (row < a.nb && vs < a.nvs && s_idx[row] >= 0) {
+          z = csub(z, uv[t][e]);
+          lpart += (k == 0 || 2 * k == a.nt ? 1.0 : 2.0) * ((double)z.x * z.x + (double)z.y * z.y);
+        } else {
+          z = make_float2(0.f, 0.f);
+        }
+        zr[t][e] = z;
+        rm = fmaxf(rm, fmaxf(fabsf(z.x), fabsf(z.y)));
+      }
+    }
+    lpart = wave_sum(lpart);
+    rm = wave_max(rm);
+    if (lane == 0) {
+      s_red[wave] = lpart;
+      s_max[wave] = rm;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < WS_CW; ++w) tot += s_red[w];
+    a.loss_part[logical] = tot;
+  }
+  const float2 ss = scale_of(s_max, WS_CW);
+
+  // adjoint, without barriers: G_k = D_b^H Res_k.  Each compute wave owns the
+  // receiver tiles wave, wave + WS_CW, ...; it loads its tile's A operand (conj D:
+  // eight batch rows of one receiver per lane and k-step) from L2 straight into
+  // registers, splitting it there (the next tile's values are in flight during
+  // the current tile's products).  The residual planes in LDS are the B operand.
+  if (compute) {
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (rt0 + t) * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+        put1(rsp(0, col, row), rsp(1, col, row), zr[t][e].x * ss.x);
+        put1(rsp(2, col, row), rsp(3, col, row), zr[t][e].y * ss.x);
+      }
+    }
+  }
+  __syncthreads();  // the last barrier: the loader waves are done
+  if (!compute) return;
+  const int nrt = (a.nr + 15) / 16;
+  auto load_tile = [&](float2 (&d)[2][8], int mt) {  // clamped: always in bounds
+    const int r = min(mt * 16 + lr, a.nr - 1);
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) d[kk][e] = a.Df[d_at(kk * 32 + lq * 8 + e, r)];
+  };
+  float2 dn[2][8];
+  load_tile(dn, min(wave, nrt - 1));
+#pragma unroll 1
+  for (int mt = wave; mt < nrt; mt += WS_CW) {
+    float2 dc[2][8];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dc[kk][e] = dn[kk][e];
+    load_tile(dn, min(mt + WS_CW, nrt - 1));
+    const int r = mt * 16 + lr;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (!d_ok(kk * 32 + lq * 8 + e, r)) dc[kk][e] = make_float2(0.f, 0.f);
+    float2 sd = make_float2(1.f, 1.f);
+    if constexpr (T::F16) {
+      float m = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(dc[kk][e].x), fabsf(dc[kk][e].y)));
+      sd = pow2_scale_pair(wave_max(m));
+    }
+    V arh[2], arl[2], aih[2], ail[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        E h, l;
+        T::split(dc[kk][e].x * sd.x, h, l);
+        arh[kk][e] = h;
+        arl[kk][e] = l;
+        T::split(-dc[kk][e].y * sd.x, h, l);  // conj
+        aih[kk][e] = h;
+        ail[kk][e] = l;
+      }
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {  // not unrolled: the B operands of one column tile at a time
+      floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const int b = kk * 32 + lq * 8, col = nt * 16 + lr;
+        const V brh = *reinterpret_cast<const V*>(rsp(0, col, b));
+        const V brl = *reinterpret_cast<const V*>(rsp(1, col, b));
+        const V bih = *reinterpret_cast<const V*>(rsp(2, col, b));
+        const V bil = *reinterpret_cast<const V*>(rsp(3, col, b));
+        cmma3<T>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im);
+      }
+      if constexpr (T::F16) {
+        re = (re * sd.y) * ss.y;
+        im = (im * sd.y) * ss.y;
+      }
+      const int blk = blk0 + nt;
+      if (blk < a.nvb) {
+        const int rb = mt * 16 + lq * 4;
+        float2* fw = a.F + (long long)rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+      }
+    }
+  }
+}
+
+template <int PREC>
+hipError_t launch_split_ws(const GemmArgs& a, hipStream_t s) {
+  using C = SCfg<4, 4>;
+  constexpr size_t sm = 2 * sizeof(typename SplitT<PREC>::E) * C::DSZ +
+                        sizeof(float2) * 2 * C::KCMAX * (C::NW + 2);
+  const int ncg = (a.nvb + 3) / 4;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split_ws<PREC>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipLaunchKernelGGL(k_gemm_split_ws<PREC>, dim3(a.nf * ncg), dim3(WS_THREADS), sm, s, a);
+  return hipGetLastError();
+}
+
 template <int PREC, int NBT, int TNB, int KIND>
 hipError_t launch_one(const GemmArgs& a, hipStream_t s) {
   using C = SCfg<NBT, TNB>;
@@ -772,6 +1208,7 @@ hipError_t launch_split_prec(int kind, const GemmArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   if (a.nb <= 32) return launch_split_cfg<PREC, 2, 2>(kind, a, s);
+  if (kind == GK_FUSED) return launch_split_ws<PREC>(a, s);
   return launch_split_cfg<PREC, 4, 4>(kind, a, s);
 }
 
