@@ -788,7 +788,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   const int total = a.nf * ncg;
   const int bid = blockIdx.x, full = (total / 8) * 8;
   const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
-  const int k = logical / ncg, cg = logical % ncg;
+  const int k = logical / ncg, cg = logical % ncg;  // the column groups of one frequency share an XCD
   const int blk0 = cg * 4;
   const long long rowstride = (long long)a.nvb * a.nf * CB;
   const int nc = (a.nr + KC - 1) / KC;
