@@ -504,6 +504,253 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   }
 }
 
+// Float32 fused products for 33..64 batch rows: a warp-specialised workgroup of
+// twelve waves.  Four loader waves keep three 64-receiver chunks of R_k (96 KB)
+// in flight in their registers and pass each through a two-slot LDS ring; eight
+// compute waves stage D_{b,k} chunks (double-buffered) and run the forward
+// 16x16x4 products, one barrier per chunk.  The adjoint has no barrier: each
+// compute wave owns receiver tiles and loads its A operand (conj D, one batch
+// row group per k-step) from L2 straight into registers.  All loads are
+// unconditional (addresses clamped into the arrays, zeros applied where the
+// values are used), so that each wait covers only the loads it needs.
+constexpr int WF_DEPTH = 3;
+constexpr int WF_CW = 8;                      // compute waves (two per SIMD)
+constexpr int WF_LW = 4;                      // loader waves
+constexpr int WF_THREADS = 64 * (WF_CW + WF_LW);
+constexpr int WF_KC = 64;                     // receivers per chunk
+constexpr int WF_DP = WF_KC + 4;              // D slot row pitch [b][r] (complex)
+constexpr int WF_RP = 64 + 16;                // ring / residual row pitch [r or b][col]
+constexpr size_t WF_SMEM = sizeof(float2) * (2 * 64 * WF_DP + 2 * WF_KC * WF_RP);
+
+__global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
+  constexpr int MB = 64, NW = 64, KC = WF_KC;
+  constexpr int NCT = 64 * WF_CW, NLT = 64 * WF_LW;
+  constexpr int LPT = KC * NW / 2 / NLT;      // float4 per loader thread per chunk
+  constexpr int FPT = MB * (KC / 2) / NCT;    // D float4 per compute thread per chunk
+  constexpr int TPC = 2;                      // forward row tiles per compute wave
+  constexpr int RING = KC * WF_RP, DSL = MB * WF_DP;
+  static_assert(LPT * NLT == KC * NW / 2 && FPT * NCT == MB * (KC / 2), "split");
+  extern __shared__ float2 smem_f2[];
+  float2* s_d = smem_f2;                      // two D slots [b][r]
+  float2* s_ring = smem_f2 + 2 * DSL;         // two R slots [r][col]
+  float2* s_res = s_ring;                     // residual [b][col], after the forward
+  __shared__ int s_idx[MB];
+  __shared__ long long s_drow[MB];
+  __shared__ double s_red[WF_CW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool compute = wave < WF_CW;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ncg = (a.nvb + 3) / 4;
+  const int total = a.nf * ncg;
+  const int bid = blockIdx.x, full = (total / 8) * 8;
+  const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
+  const int k = logical / ncg, cg = logical % ncg;  // the column groups of one frequency share an XCD
+  const int blk0 = cg * 4;
+  const long long rowstride = (long long)a.nvb * a.nf * CB;
+  const int nc = (a.nr + KC - 1) / KC;
+  const int nt_w = wave & 3, rt0 = (wave >> 2) * TPC;
+  const int li = tid - NCT;
+
+  for (int b = tid; b < MB; b += WF_THREADS) {
+    int s = -1;
+    if (b < a.nb) {
+      s = a.idx[b];
+      if (s < 0 || s >= a.ns) s = -1;
+    }
+    s_idx[b] = s;
+    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+  }
+  __syncthreads();
+
+  const long long drow0 = (long long)k * a.ns * a.nrp;
+  auto d_at = [&](int b, int r) -> long long {  // always in bounds
+    const long long off = s_drow[b];
+    return (off >= 0 ? off : drow0) + (r < a.nr ? r : 0);
+  };
+  auto d_ok = [&](int b, int r) { return s_drow[b] >= 0 && r < a.nr; };
+
+  if (compute) {
+    float4 dv[FPT];
+    auto load_d = [&](int c) {
+#pragma unroll
+      for (int q = 0; q < FPT; ++q) {
+        const int i = tid + NCT * q;
+        dv[q] = *reinterpret_cast<const float4*>(a.Df + d_at(i / (KC / 2), c * KC + 2 * (i % (KC / 2))));
+      }
+    };
+    auto stage_d = [&](int sl, int c) {
+#pragma unroll
+      for (int q = 0; q < FPT; ++q) {
+        const int i = tid + NCT * q;
+        const int b = i / (KC / 2), rr = 2 * (i % (KC / 2)), r = c * KC + rr;
+        float4 v = d_ok(b, r) ? dv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r + 1 >= a.nr) v.z = v.w = 0.f;
+        *reinterpret_cast<float4*>(s_d + sl * DSL + b * WF_DP + rr) = v;
+      }
+    };
+    floatx4 ar[TPC], ai[TPC];
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+      ar[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ai[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    load_d(0);
+    __syncthreads();
+    stage_d(0, 0);
+    load_d(1);
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < nc; ++c) {
+      const int sl = c & 1;
+      const int steps = (min(KC, a.nr - c * KC) + 3) / 4;
+      const float2* ring = s_ring + sl * RING + lq * WF_RP + nt_w * 16 + lr;
+      const float2* dsl = s_d + sl * DSL + (rt0 * 16 + lr) * WF_DP + lq;
+      for (int ks = 0; ks < steps; ++ks) {
+        const float2 bv = ring[ks * 4 * WF_RP];
+#pragma unroll
+        for (int t = 0; t < TPC; ++t) {
+          const float2 dv2 = dsl[t * 16 * WF_DP + ks * 4];
+          ar[t] = mfma4(dv2.x, bv.x, ar[t]);
+          ar[t] = mfma4(-dv2.y, bv.y, ar[t]);
+          ai[t] = mfma4(dv2.x, bv.y, ai[t]);
+          ai[t] = mfma4(dv2.y, bv.x, ai[t]);
+        }
+      }
+      stage_d(sl ^ 1, c + 1);  // the next chunk into the slot chunk c - 1 used
+      load_d(c + 2);
+      __syncthreads();
+    }
+
+    // residual and float64 loss partial
+    float2 uv[TPC][4];
+#pragma unroll
+    for (int t = 0; t < TPC; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (rt0 + t) * 16 + lq * 4 + e, vs = blk0 * CB + nt_w * 16 + lr;
+        const int s = row < a.nb ? max(s_idx[row], 0) : 0;
+        uv[t][e] = a.Uf[((size_t)k * a.ns + s) * a.nvsp + min(vs, a.nvsp - 1)];
+      }
+    double lpart = 0.0;
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = (rt0 + t) * 16 + lq * 4 + e, col = nt_w * 16 + lr;
+        const int vs = blk0 * CB + col;
+        float2 z = make_float2(ar[t][e], ai[t][e]);
+        if (row < a.nb && vs < a.nvs && s_idx[row] >= 0) {
+          z = csub(z, uv[t][e]);
+          lpart += (k == 0 || 2 * k == a.nt ? 1.0 : 2.0) * ((double)z.x * z.x + (double)z.y * z.y);
+        } else {
+          z = make_float2(0.f, 0.f);
+        }
+        s_res[row * WF_RP + col] = z;  // the ring is no longer read
+      }
+    }
+    lpart = wave_sum(lpart);
+    if (lane == 0) s_red[wave] = lpart;
+  } else {
+    float4 rq[WF_DEPTH][LPT];
+    auto issue = [&](float4 (&dst)[LPT], int c) {
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const int i = li + NLT * q;
+        const int rr = i / (NW / 2), cp = 2 * (i % (NW / 2));
+        const int r = min(c * KC + rr, a.nr - 1), blk = min(blk0 + cp / CB, a.nvb - 1);
+        dst[q] = *reinterpret_cast<const float4*>(a.F + (long long)r * rowstride +
+                                                  ((long long)blk * a.nf + k) * CB + cp % CB);
+      }
+    };
+    auto put_ring = [&](const float4 (&src)[LPT], int c) {
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const int i = li + NLT * q;
+        const int rr = i / (NW / 2), cp = 2 * (i % (NW / 2));
+        const bool ok = c * KC + rr < a.nr && blk0 + cp / CB < a.nvb;
+        *reinterpret_cast<float4*>(s_ring + (c & 1) * RING + rr * WF_RP + cp) =
+            ok ? src[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    issue(rq[0], 0);
+    issue(rq[1], 1);
+    issue(rq[2], 2);
+    __syncthreads();
+    put_ring(rq[0], 0);
+    issue(rq[0], 3);
+    __syncthreads();
+    int c0 = 0;
+#pragma unroll 1
+    for (; c0 + WF_DEPTH <= nc; c0 += WF_DEPTH) {
+#pragma unroll
+      for (int u = 0; u < WF_DEPTH; ++u) {  // chunk c + 1 into the slot chunk c - 1 used
+        const int c = c0 + u;
+        put_ring(rq[(u + 1) % WF_DEPTH], c + 1);
+        issue(rq[(u + 1) % WF_DEPTH], c + 1 + WF_DEPTH);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WF_DEPTH - 1; ++u) {
+      const int c = c0 + u;
+      if (c < nc) {
+        put_ring(rq[(u + 1) % WF_DEPTH], c + 1);
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();  // residual complete; the last barrier of the loader waves
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < WF_CW; ++w) tot += s_red[w];
+    a.loss_part[logical] = tot;
+  }
+  if (!compute) return;
+
+  // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
+  const int nrt = (a.nr + 15) / 16;
+  auto load_tile = [&](float2 (&d)[16], int mt) {  // conj D operand: b = ks*4 + lq
+    const int r = min(mt * 16 + lr, a.nr - 1);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) d[ks] = a.Df[d_at(ks * 4 + lq, r)];
+  };
+  float2 dn[16];
+  load_tile(dn, min(wave, nrt - 1));
+#pragma unroll 1
+  for (int mt = wave; mt < nrt; mt += WF_CW) {
+    float2 dc[16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) dc[ks] = dn[ks];
+    load_tile(dn, min(mt + WF_CW, nrt - 1));
+    const int r = mt * 16 + lr;
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+      if (!d_ok(ks * 4 + lq, r)) dc[ks] = make_float2(0.f, 0.f);
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+      floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+      const float2* res = s_res + lq * WF_RP + nt * 16 + lr;
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const float2 sv = res[ks * 4 * WF_RP];
+        re = mfma4(dc[ks].x, sv.x, re);
+        re = mfma4(dc[ks].y, sv.y, re);
+        im = mfma4(dc[ks].x, sv.y, im);
+        im = mfma4(-dc[ks].y, sv.x, im);
+      }
+      const int blk = blk0 + nt;
+      if (blk < a.nvb) {
+        const int rb = mt * 16 + lq * 4;
+        float2* fw = a.F + (long long)rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+      }
+    }
+  }
+}
+
 // Persistent, software-pipelined form of the fused product for float32, at most
 // 16 batch rows and at most PIPE_KC receivers (one chunk).  Each workgroup walks a
 // contiguous range of (frequency, column group) items: while one item's products
@@ -720,6 +967,15 @@ hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;  // not reached: nb > 16 went to launch_gemm_split
   } else {
     if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
+    if constexpr (PREC == MDD_PREC_FP32) {
+      if (kind == GK_FUSED) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_ws),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)WF_SMEM);
+        const int ncg = (a.nvb + 3) / 4;
+        hipLaunchKernelGGL(k_gemm_ws, dim3(a.nf * ncg), dim3(WF_THREADS), WF_SMEM, s, a);
+        return hipGetLastError();
+      }
+    }
     return launch_cfg<PREC, 4, 4>(kind, a, s);
   }
 }
