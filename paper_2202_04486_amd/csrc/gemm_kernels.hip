@@ -603,10 +603,10 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
 #pragma unroll 1
     for (int c = 0; c < nc; ++c) {
       const int sl = c & 1;
-      const int steps = (min(KC, a.nr - c * KC) + 3) / 4;
       const float2* ring = s_ring + sl * RING + lq * WF_RP + nt_w * 16 + lr;
       const float2* dsl = s_d + sl * DSL + (rt0 * 16 + lr) * WF_DP + lq;
-      for (int ks = 0; ks < steps; ++ks) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {  // rows past nr are zeros in both operands
         const float2 bv = ring[ks * 4 * WF_RP];
 #pragma unroll
         for (int t = 0; t < TPC; ++t) {
