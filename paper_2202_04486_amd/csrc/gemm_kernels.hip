@@ -757,9 +757,9 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
 // run, the next item's R_k fragments and data entries are already in flight, and
 // D_{b,k} stays in LDS for as long as the frequency does not change.
 constexpr int PIPE_KC = 224;
-constexpr int PIPE_WGS = 512;   // 2 workgroups on each of the 256 CUs (its register use)
+constexpr int PIPE_WGS = 768;   // 3 workgroups on each of the 256 CUs (registers capped to fit)
 
-__global__ __launch_bounds__(256) void k_gemm_pipe(GemmArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_pipe(GemmArgs a) {
   constexpr int MB = 16, NW = 16, DST = PIPE_KC + 2, RST = NW + 1;
   constexpr int KSW = PIPE_KC / 4 / 4;        // k-steps per wave (4 waves split K)
   constexpr int PAIRS = PIPE_KC / 2;          // float4 pairs per D row
