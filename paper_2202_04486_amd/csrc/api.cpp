@@ -19,7 +19,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_nt(int nt) { return nt == 128 || nt == 256 || nt == 512 || nt == 1024; }
 
 struct Layout {
-  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, total;
+  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, total;
 };
 
 Layout make_layout(const mdd_dims& d) {
@@ -42,6 +42,7 @@ Layout make_layout(const mdd_dims& d) {
   L.bsp = take(c8 * d.nb_max * nvb * d.nf * CB);
   L.lossp = take(sizeof(double) * d.nf * nvb);
   L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
+  L.dmx = take(sizeof(float) * d.nf);               // per-frequency max |D| (fp16 scaling)
   L.total = o;
   return L;
 }
@@ -95,6 +96,7 @@ struct mdd_plan {
   float2* Bsp() const { return at<float2>(L.bsp); }
   double* lossp() const { return at<double>(L.lossp); }
   double* gnp() const { return at<double>(L.gnp); }
+  float* dmx() const { return at<float>(L.dmx); }
 
   template <class Fn>
   mdd_status run(int kclass, Fn&& fn) {
@@ -142,6 +144,7 @@ struct mdd_plan {
     g.Bsp = Bsp();
     g.idx = idx;
     g.loss_part = lossp();
+    g.dmax = d.precision == MDD_PREC_FP16X3 ? dmx() : nullptr;
     g.ns = d.ns;
     g.nr = d.nr;
     g.nrp = nrp;
@@ -248,6 +251,10 @@ mdd_status mdd_set_kernel(mdd_plan* p, const float* d) {
   a.s_k = (long long)p->d.ns * p->nrp;
   a.tw = p->tw();
   MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  if (p->d.precision == MDD_PREC_FP16X3)
+    MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] {
+      return launch_freq_absmax(p->Df(), p->d.nf, (long long)p->d.ns * p->nrp, p->dmx(), p->stream);
+    }));
   p->kernel_set = true;
   return MDD_OK;
 }

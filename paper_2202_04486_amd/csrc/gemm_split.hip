@@ -14,8 +14,9 @@
 // conjugate as [r][b] for the adjoint (the two are never live together, so
 // they share LDS), and the residual as [column][b].  R_k, the right operand of
 // the forward product, goes from HBM to registers and is split there by the
-// one wave that uses it.  fp16 carries a power-of-two scale per receiver chunk
-// and per residual block so that the low halves stay normal.
+// one wave that uses it.  fp16 carries power-of-two scales so that the low halves
+// stay normal: one per frequency for D_{b,k} (from its largest |D|, found when the
+// kernel is set), one per receiver chunk of R_k and one per residual block.
 #include <type_traits>
 
 #include "device_common.h"
@@ -246,14 +247,12 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
         for (int e = 0; e < 8; ++e) bfr[q][e] = bnx[q][e];
       float2 sd = make_float2(1.f, 1.f), sr = make_float2(1.f, 1.f);
       if constexpr (T::F16) {
-        float bm = 0.f, dm = 0.f;
+        float bm = 0.f;
 #pragma unroll
         for (int q = 0; q < C::KSW; ++q)
 #pragma unroll
           for (int e = 0; e < 8; ++e) bm = fmaxf(bm, fmaxf(fabsf(bfr[q][e].x), fabsf(bfr[q][e].y)));
-#pragma unroll
-        for (int q = 0; q < C::FPT; ++q) dm = fmaxf(dm, amax4(dv[q]));
-        sd = pow2_scale_pair(block_max(dm));
+        sd = pow2_scale_pair(a.dmax[k]);
         sr = pow2_scale_pair(block_max(bm));
       }
       __syncthreads();  // the previous chunk's planes are no longer read
@@ -415,14 +414,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
   for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
     const int len = min(KCMAX, a.nr - r0);
     float2 sd = make_float2(1.f, 1.f);
-    if constexpr (T::F16) {
-      float dm = 0.f;
-#pragma unroll
-      for (int q = 0; q < C::APT; ++q)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) dm = fmaxf(dm, fmaxf(fabsf(dj[q][h].x), fabsf(dj[q][h].y)));
-      sd = pow2_scale_pair(block_max(dm));
-    }
+    if constexpr (T::F16) sd = pow2_scale_pair(a.dmax[k]);
     __syncthreads();  // residual planes complete; previous D planes no longer read
 #pragma unroll
     for (int q = 0; q < C::APT; ++q) {
@@ -554,7 +546,6 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
   // D_{b,k} -> split planes; returns the (fp16) scale and its inverse
   auto stage_d = [&](int k) -> float2 {
     float4 dv[DPT];
-    float m = 0.f;
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int i = tid + 256 * q;
@@ -566,15 +557,9 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
         if (rr + 1 >= a.nr) v.z = v.w = 0.f;
       }
       dv[q] = v;
-      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
     }
     float2 sd = make_float2(1.f, 1.f);
-    if constexpr (T::F16) {
-      m = wave_max(m);
-      if (lane == 0) s_mx[wave] = m;
-      __syncthreads();
-      sd = pow2_scale_pair(fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
-    }
+    if constexpr (T::F16) sd = pow2_scale_pair(a.dmax[k]);
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int i = tid + 256 * q;
@@ -777,7 +762,6 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   __shared__ int s_idx[MB];
   __shared__ long long s_drow[MB];
   __shared__ double s_red[WS_CW];
-  __shared__ float s_dmax[3][WS_CW];  // fp16: per D chunk (mod 3), per compute wave
   __shared__ float s_rmax[2][WS_LW];  // fp16: per ring slot, per loader wave
   __shared__ float s_max[WS_CW];
 
@@ -842,6 +826,9 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     if constexpr (T::F16) return pow2_scale_pair(maxn(v, n));
     else return make_float2(1.f, 1.f);
   };
+  // fp16: one power-of-two scale for D_{b,k}, from the frequency's largest |D|
+  float2 sdk = make_float2(1.f, 1.f);
+  if constexpr (T::F16) sdk = pow2_scale_pair(a.dmax[k]);
 
   // ---- loader side: R_k chunk c (rows c*KC ..) of the four column blocks.  The
   // loads are unconditional (addresses clamped into the array) so that nothing
@@ -892,17 +879,6 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       const int i = tid + NCT * q;
       dv[q] = *reinterpret_cast<const float4*>(a.Df + d_at(i / (KC / 2), c * KC + 2 * (i % (KC / 2))));
     }
-    if constexpr (T::F16) {
-      float m = 0.f;
-#pragma unroll
-      for (int q = 0; q < FPT; ++q) {
-        const int i = tid + NCT * q;
-        const int b = i / (KC / 2), r = c * KC + 2 * (i % (KC / 2));
-        if (d_ok(b, r)) m = fmaxf(m, r + 1 < a.nr ? amax4(dv[q]) : fmaxf(fabsf(dv[q].x), fabsf(dv[q].y)));
-      }
-      m = wave_max(m);
-      if (lane == 0) s_dmax[c % 3][wave] = m;
-    }
   };
   auto stage_dfwd = [&](int sl, float sd, int c) {
 #pragma unroll
@@ -929,14 +905,14 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     // prologue: D chunk 0 staged, chunk 1 in flight
     load_dfwd(0);
     __syncthreads();
-    stage_dfwd(0, scale_of(s_dmax[0], WS_CW).x, 0);
+    stage_dfwd(0, sdk.x, 0);
     load_dfwd(1);  // chunks past the end load clamped addresses and stage zeros
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < nc; ++c) {
       const int sl = c & 1;
       const int len = min(KC, a.nr - c * KC);
-      const float2 sd = scale_of(s_dmax[c % 3], WS_CW), sr = scale_of(s_rmax[sl], WS_LW);
+      const float2 sd = sdk, sr = scale_of(s_rmax[sl], WS_LW);
       floatx4 cre[TPC], cim[TPC];
 #pragma unroll
       for (int t = 0; t < TPC; ++t) {
@@ -987,7 +963,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       }
       // the next D chunk into the other slot (last read by chunk c - 1); unconditional
       // so that the loads in flight are the same on every path
-      stage_dfwd(sl ^ 1, scale_of(s_dmax[(c + 1) % 3], WS_CW).x, c + 1);
+      stage_dfwd(sl ^ 1, sdk.x, c + 1);
       load_dfwd(c + 2);
       __syncthreads();
     }
@@ -1113,15 +1089,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
         if (!d_ok(kk * 32 + lq * 8 + e, r)) dc[kk][e] = make_float2(0.f, 0.f);
-    float2 sd = make_float2(1.f, 1.f);
-    if constexpr (T::F16) {
-      float m = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(dc[kk][e].x), fabsf(dc[kk][e].y)));
-      sd = pow2_scale_pair(wave_max(m));
-    }
+    const float2 sd = sdk;
     V arh[2], arl[2], aih[2], ail[2];
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)

@@ -74,6 +74,7 @@ struct GemmArgs {
   float2* Bsp;            // [nb][nvb][nf][CB]   batch spectra
   const int32_t* idx;
   double* loss_part;      // [gridDim.x * gridDim.y]
+  const float* dmax;      // [nf] largest |Re|, |Im| of D_k (fp16 split forms; else NULL)
   int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
 };
 
@@ -90,6 +91,8 @@ hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStre
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
                           hipStream_t s);
+hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out,
+                              hipStream_t s);
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,
                         double* lam_out, hipStream_t s);
 

@@ -119,10 +119,30 @@ __global__ __launch_bounds__(256) void k_sigma(const float2* Df, int ns, int nr,
   if (tid == 0) lam_out[k] = lam;
 }
 
+// Largest |Re| or |Im| of D_k over all sources and receivers, per frequency (the
+// fp16 split forms scale D_{b,k} by a power of two derived from it).  One
+// workgroup per frequency; a maximum does not depend on the order.
+__global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long per_freq, float* out) {
+  const float2* x = Df + (long long)blockIdx.x * per_freq;
+  float m = 0.f;
+  for (long long i = threadIdx.x; i < per_freq; i += 256) m = fmaxf(m, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __shared__ float s_m[4];
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+}
+
 }  // namespace
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_freq_absmax, dim3(nf), dim3(256), 0, s, Df, per_freq, out);
   return hipGetLastError();
 }
 
