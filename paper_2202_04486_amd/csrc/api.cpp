@@ -19,7 +19,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_nt(int nt) { return nt == 128 || nt == 256 || nt == 512 || nt == 1024; }
 
 struct Layout {
-  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, total;
+  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, red2, total;
 };
 
 Layout make_layout(const mdd_dims& d) {
@@ -43,6 +43,7 @@ Layout make_layout(const mdd_dims& d) {
   L.lossp = take(sizeof(double) * d.nf * nvb);
   L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
   L.dmx = take(sizeof(float) * d.nf);               // per-frequency max |D| (fp16 scaling)
+  L.red2 = take(sizeof(double) * 512);              // two-level reduction stage
   L.total = o;
   return L;
 }
@@ -97,6 +98,7 @@ struct mdd_plan {
   double* lossp() const { return at<double>(L.lossp); }
   double* gnp() const { return at<double>(L.gnp); }
   float* dmx() const { return at<float>(L.dmx); }
+  double* red2() const { return at<double>(L.red2); }
 
   template <class Fn>
   mdd_status run(int kclass, Fn&& fn) {
@@ -180,6 +182,7 @@ struct mdd_plan {
     r.n_gn = d.nr * nvb * trace_update_split(d.nt);
     r.loss_out = loss_out;
     r.gnorm2_out = gnorm2_out;
+    r.stage = red2();
     return run(MDD_KC_REDUCE, [&] { return launch_reduce(r, stream); });
   }
 };

@@ -37,7 +37,11 @@ struct ReduceArgs {
   int n_gn;
   double* loss_out;
   double* gnorm2_out;
+  double* stage;          // [2 * 256] for the two-level sum of long partial arrays
 };
+
+// Partial arrays longer than this are summed in two levels (fixed order either way).
+constexpr int RED_TWO_LEVEL = 32768;
 
 // One launch of the trace kernel: a grid of tiles, tile (row, cb) holding the
 // traces (row, cb*CB + c), c < CB, of a [rows][ncols][nt] time-domain array.

@@ -34,6 +34,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ReduceArgs a) {
   }
 }
 
+// First level of a two-level sum for long partial arrays: block j of row y adds
+// slice j of array y (y = 0: loss partials, 1: gradient-norm partials) in a fixed
+// order.  The second level is k_reduce over the 2 * RED_SLICES results.
+constexpr int RED_SLICES = 256;
+__global__ __launch_bounds__(256) void k_presum(const double* loss_part, int n_loss, const double* gn_part,
+                                                int n_gn, double* stage) {
+  __shared__ double red[4];
+  const double* p = blockIdx.y == 0 ? loss_part : gn_part;
+  const int n = blockIdx.y == 0 ? n_loss : n_gn;
+  const int per = (n + RED_SLICES - 1) / RED_SLICES;
+  const int lo = min(n, (int)blockIdx.x * per), hi = min(n, lo + per);
+  const double v = block_fixed_sum<256>(p + lo, hi - lo, red);
+  if (threadIdx.x == 0) stage[blockIdx.y * RED_SLICES + blockIdx.x] = v;
+}
+
 __global__ void k_row_sum(const double* part, int rows, int cols, double scale, double* out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < rows) {
@@ -137,6 +152,17 @@ __global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long
 }  // namespace
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  if (a.stage && (a.n_loss > RED_TWO_LEVEL || a.n_gn > RED_TWO_LEVEL)) {
+    hipLaunchKernelGGL(k_presum, dim3(RED_SLICES, 2), dim3(256), 0, s, a.loss_part, a.n_loss,
+                       a.gn_part, a.n_gn, a.stage);
+    ReduceArgs b = a;
+    b.loss_part = a.stage;
+    b.n_loss = a.n_loss > 0 ? RED_SLICES : 0;
+    b.gn_part = a.stage + RED_SLICES;
+    b.n_gn = a.n_gn > 0 ? RED_SLICES : 0;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, b);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, a);
   return hipGetLastError();
 }
