@@ -138,3 +138,18 @@ def test_split_small_batches(prec, nb, nr):
     assert abs(loss.item() - lo) <= 1e-3 * lo
     G2, loss2, _ = plan.mdd_stoch_grad(T(r), T(idx.astype(np.int32), torch.int32))
     assert torch.equal(G, G2) and torch.equal(loss, loss2)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16x3", 1e-3)])
+@pytest.mark.parametrize("nr,nvs", [(1, 1), (5, 3), (17, 65)])
+def test_large_batch_small_operators(prec, tol, nr, nvs):
+    """Batches of 33..64 (the warp-specialised fused kernels) on one or a few receivers and
+    virtual sources: a single partial receiver chunk and column groups mostly out of range."""
+    ns, nt, nf, nb = 48, 128, 65, 40
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nr * 7 + nvs)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, precision=prec)
+    idx = batch(ns, nb, seed=nr)
+    G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= tol
+    assert abs(loss.item() - lo) <= tol * lo
