@@ -72,10 +72,12 @@ typedef int32_t mdd_status;
 /* Plan flags. */
 #define MDD_FLAG_STORE_RF 1 /* mdd_step also writes the spectra of the updated model so the
                                next mdd_step on the same R skips its forward transform */
+#define MDD_FLAG_FULL_GRAD 2 /* reserve a second spectra buffer and the list of all sources
+                                for mdd_full_grad / mdd_full_step */
 
 /* Sizes.  ns sources, nr receivers, nvs virtual sources, nt time samples
  * (128, 256, 512 or 1024), nf retained one-sided frequency bins (1..nt/2+1),
- * nb_max the largest batch any call on this plan will use (1..ns, <= 256). */
+ * nb_max the largest batch any call on this plan will use (1..ns, <= 64). */
 typedef struct mdd_dims {
   int32_t ns, nr, nvs, nt, nf, nb_max;
   int32_t precision; /* MDD_PREC_* */
@@ -165,6 +167,25 @@ mdd_status mdd_stoch_grad(mdd_plan* plan, const float* R, const int32_t* idx, in
  * values at the point where the gradient was taken). */
 mdd_status mdd_step(mdd_plan* plan, float* R, float* s0, float* s1, const mdd_opt* opt,
                     const int32_t* idx, int32_t nb, double* loss_out, double* gnorm2_out);
+
+/* Gradient of the whole finite-sum functional (Theory section: the batch is every
+ * source; Appendix A: one such iteration costs what one stochastic epoch costs,
+ * less the per-batch model transforms):
+ *   loss = 1/2 sum_{s < ns} || p-_s - P+_s R ||^2                  (float64)
+ *   G    = C_c [ - sum_{s < ns} P+_s^H (p-_s - P+_s R) ],  gnorm2 = || G ||^2
+ * The sources are taken in order in batches of nb_max; R is transformed once and
+ * the batches' adjoint products accumulate in the second spectra buffer.
+ * G_out [nr][nvs][nt] float32; loss_out / gnorm2_out device float64 (may be NULL).
+ * Needs kernel, data and MDD_FLAG_FULL_GRAD (MDD_ESTATE otherwise). */
+mdd_status mdd_full_grad(mdd_plan* plan, const float* R, float* G_out, double* loss_out,
+                         double* gnorm2_out);
+
+/* One full-gradient iteration in place: the gradient of mdd_full_grad at R (for
+ * MDD_OPT_NSGD at R + mu s0), then the update of mdd_step.  With MDD_OPT_SGD and
+ * lr = kappa 2 / sigma_max^2 this is the Landweber iteration of Appendix B.
+ * Needs kernel, data and MDD_FLAG_FULL_GRAD. */
+mdd_status mdd_full_step(mdd_plan* plan, float* R, float* s0, float* s1, const mdd_opt* opt,
+                         double* loss_out, double* gnorm2_out);
 
 /* Forget stored model spectra (MDD_FLAG_STORE_RF): call after changing R
  * other than through mdd_step. */

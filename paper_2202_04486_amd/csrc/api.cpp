@@ -19,7 +19,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_nt(int nt) { return nt == 128 || nt == 256 || nt == 512 || nt == 1024; }
 
 struct Layout {
-  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, red2, total;
+  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, red2, f2, sidx, lossb, total;
 };
 
 Layout make_layout(const mdd_dims& d) {
@@ -44,6 +44,10 @@ Layout make_layout(const mdd_dims& d) {
   L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
   L.dmx = take(sizeof(float) * d.nf);               // per-frequency max |D| (fp16 scaling)
   L.red2 = take(sizeof(double) * 512);              // two-level reduction stage
+  const bool full = (d.flags & MDD_FLAG_FULL_GRAD) != 0;  // full gradient: G buffer, sources, losses
+  L.f2 = take(full ? c8 * d.nr * nvb * d.nf * CB : 0);
+  L.sidx = take(full ? sizeof(int32_t) * d.ns : 0);
+  L.lossb = take(full ? sizeof(double) * ((d.ns + d.nb_max - 1) / d.nb_max) : 0);
   L.total = o;
   return L;
 }
@@ -56,7 +60,7 @@ mdd_status check_dims(const mdd_dims* d) {
   if (d->nf > d->nt / 2 + 1) return MDD_ESHAPE;
   if (d->nb_max > d->ns || d->nb_max > NB_LIMIT) return MDD_ESHAPE;
   if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_BF16) return MDD_EUNSUPPORTED;
-  if (d->flags & ~MDD_FLAG_STORE_RF) return MDD_EINVAL;
+  if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD)) return MDD_EINVAL;
   return MDD_OK;
 }
 
@@ -79,6 +83,9 @@ struct mdd_plan {
   const float* spec_model = nullptr;
   const float* spec_vel = nullptr;
   double spec_mu = 0.0;
+  // MDD_FLAG_FULL_GRAD: the two spectra buffers swap roles when a full step stores the
+  // next model's spectra where the gradient was accumulated.
+  bool fswap = false;
   int32_t last_hip = 0;
   bool prof = false;
   int cap = 0, nrec = 0;
@@ -93,12 +100,16 @@ struct mdd_plan {
   double* oob() const { return at<double>(L.oob); }
   double* oobp() const { return at<double>(L.oobp); }
   int32_t* onset() const { return at<int32_t>(L.onset); }
-  float2* F() const { return at<float2>(L.f); }
+  float2* F() const { return at<float2>(fswap ? L.f2 : L.f); }
+  float2* F2() const { return at<float2>(fswap ? L.f : L.f2); }
   float2* Bsp() const { return at<float2>(L.bsp); }
   double* lossp() const { return at<double>(L.lossp); }
   double* gnp() const { return at<double>(L.gnp); }
   float* dmx() const { return at<float>(L.dmx); }
   double* red2() const { return at<double>(L.red2); }
+  int32_t* sidx() const { return at<int32_t>(L.sidx); }
+  double* lossb() const { return at<double>(L.lossb); }
+  bool full() const { return (d.flags & MDD_FLAG_FULL_GRAD) != 0; }
 
   template <class Fn>
   mdd_status run(int kclass, Fn&& fn) {
@@ -179,6 +190,43 @@ struct mdd_plan {
     r.nb = nb;
     r.ns = d.ns;
     r.gn_part = gnp();
+    r.n_gn = gnorm2_out ? d.nr * nvb * trace_update_split(d.nt) : 0;
+    r.loss_out = loss_out;
+    r.gnorm2_out = gnorm2_out;
+    r.stage = red2();
+    return run(MDD_KC_REDUCE, [&] { return launch_reduce(r, stream); });
+  }
+
+  // Full gradient, products part: every source in order, batches of nb_max, the
+  // adjoint products summed into F2; batch j's loss into lossb[j].  F keeps R_k.
+  mdd_status full_products() {
+    const int nsub = (d.ns + d.nb_max - 1) / d.nb_max;
+    for (int j = 0; j < nsub; ++j) {
+      const int nb = d.ns - j * d.nb_max < d.nb_max ? d.ns - j * d.nb_max : d.nb_max;
+      const int32_t* idx = sidx() + (size_t)j * d.nb_max;
+      GemmArgs g = gemm(idx, nb);
+      g.Gout = F2();
+      g.gacc = j > 0 ? 1 : 0;
+      mdd_status st = run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, d.precision, g, stream); });
+      if (st != MDD_OK) return st;
+      st = reduce(idx, nb, true, lossb() + j, nullptr);
+      if (st != MDD_OK) return st;
+    }
+    return MDD_OK;
+  }
+
+  // Full gradient, final sums: the batches' losses in order and ||g||^2.
+  mdd_status full_reduce(double* loss_out, double* gnorm2_out) {
+    if (!loss_out && !gnorm2_out) return MDD_OK;
+    ReduceArgs r{};
+    r.loss_part = lossb();
+    r.n_loss = (d.ns + d.nb_max - 1) / d.nb_max;
+    r.loss_scale = 1.0;
+    r.oob = nullptr;
+    r.idx = nullptr;
+    r.nb = 0;
+    r.ns = d.ns;
+    r.gn_part = gnp();
     r.n_gn = d.nr * nvb * trace_update_split(d.nt);
     r.loss_out = loss_out;
     r.gnorm2_out = gnorm2_out;
@@ -186,6 +234,40 @@ struct mdd_plan {
     return run(MDD_KC_REDUCE, [&] { return launch_reduce(r, stream); });
   }
 };
+
+// Optimiser fields of the update kernel from mdd_opt; validates them.
+mdd_status update_args(const mdd_opt& o, float* s0, float* s1, TraceArgs& a, int& mode) {
+  switch (o.kind) {
+    case MDD_OPT_SGD: mode = TM_SGD; break;
+    case MDD_OPT_ADAM:
+      if (!s0 || !s1) return MDD_EINVAL;
+      if (!(o.beta1 >= 0.0 && o.beta1 < 1.0) || !(o.beta2 >= 0.0 && o.beta2 < 1.0)) return MDD_EINVAL;
+      if (!(o.eps > 0.0) || o.t < 1) return MDD_EINVAL;
+      mode = TM_ADAM;
+      break;
+    case MDD_OPT_NSGD:
+      if (!s0) return MDD_EINVAL;
+      if (!(o.mu >= 0.0 && o.mu < 1.0)) return MDD_EINVAL;
+      mode = TM_NSGD;
+      break;
+    default: return MDD_EINVAL;
+  }
+  if (!(o.lr > 0.0) || !std::isfinite(o.lr)) return MDD_EINVAL;
+  a.st0 = s0;
+  a.st1 = s1;
+  a.lr = (float)o.lr;
+  a.beta1 = (float)o.beta1;
+  a.beta2 = (float)o.beta2;
+  a.eps = (float)o.eps;
+  a.mu = (float)o.mu;
+  a.omb1 = (float)(1.0 - o.beta1);
+  a.omb2 = (float)(1.0 - o.beta2);
+  if (mode == TM_ADAM) {
+    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(o.beta1, (double)o.t)));
+    a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(o.beta2, (double)o.t)));
+  }
+  return MDD_OK;
+}
 
 #define MDD_TRY(x)                 \
   do {                             \
@@ -217,7 +299,8 @@ mdd_status mdd_plan_create(const mdd_dims* dims, void* workspace, size_t ws_byte
   p->nrp = round16(dims->nr);
   p->nvsp = round16(dims->nvs);
   p->nvb = nblocks(dims->nvs);
-  const hipError_t e = launch_twiddles(p->tw(), dims->nt, p->stream);
+  hipError_t e = launch_twiddles(p->tw(), dims->nt, p->stream);
+  if (e == hipSuccess && p->full()) e = launch_iota(p->sidx(), dims->ns, p->stream);
   if (e != hipSuccess) {
     delete p;
     return MDD_EHIP;
@@ -348,47 +431,18 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
   if (!p || !R || !opt || !idx) return MDD_EINVAL;
   if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
   if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
-  const mdd_opt& o = *opt;
-  if (!(o.lr > 0.0) || !std::isfinite(o.lr)) return MDD_EINVAL;
-  int mode;
-  switch (o.kind) {
-    case MDD_OPT_SGD: mode = TM_SGD; break;
-    case MDD_OPT_ADAM:
-      if (!s0 || !s1) return MDD_EINVAL;
-      if (!(o.beta1 >= 0.0 && o.beta1 < 1.0) || !(o.beta2 >= 0.0 && o.beta2 < 1.0)) return MDD_EINVAL;
-      if (!(o.eps > 0.0) || o.t < 1) return MDD_EINVAL;
-      mode = TM_ADAM;
-      break;
-    case MDD_OPT_NSGD:
-      if (!s0) return MDD_EINVAL;
-      if (!(o.mu >= 0.0 && o.mu < 1.0)) return MDD_EINVAL;
-      mode = TM_NSGD;
-      break;
-    default: return MDD_EINVAL;
-  }
+  TraceArgs a = p->blocked(p->F(), p->d.nr);
+  int mode = 0;
+  MDD_TRY(update_args(*opt, s0, s1, a, mode));
   const bool store = (p->d.flags & MDD_FLAG_STORE_RF) != 0;
   const float* vel = mode == TM_NSGD ? s0 : nullptr;
-  const double mu = mode == TM_NSGD ? o.mu : 0.0;
+  const double mu = mode == TM_NSGD ? opt->mu : 0.0;
   const bool have = store && p->spec_model == R && p->spec_vel == vel && p->spec_mu == mu;
   p->spec_model = nullptr;
   if (!have) MDD_TRY(p->model_fft(R, vel, mu));
   const GemmArgs g = p->gemm(idx, nb);
   MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, p->d.precision, g, p->stream); }));
-  TraceArgs a = p->blocked(p->F(), p->d.nr);
   a.model = R;
-  a.st0 = s0;
-  a.st1 = s1;
-  a.lr = (float)o.lr;
-  a.beta1 = (float)o.beta1;
-  a.beta2 = (float)o.beta2;
-  a.eps = (float)o.eps;
-  a.mu = (float)o.mu;
-  a.omb1 = (float)(1.0 - o.beta1);
-  a.omb2 = (float)(1.0 - o.beta2);
-  if (mode == TM_ADAM) {
-    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow(o.beta1, (double)o.t)));
-    a.inv_bc2 = (float)(1.0 / (1.0 - std::pow(o.beta2, (double)o.t)));
-  }
   a.store_spec = store ? 1 : 0;
   a.onset = p->mask_set ? p->onset() : nullptr;
   a.part = p->gnp();
@@ -399,6 +453,54 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
     p->spec_mu = mu;
   }
   return p->reduce(idx, nb, true, loss_out, gnorm2_out);
+}
+
+mdd_status mdd_full_grad(mdd_plan* p, const float* R, float* G_out, double* loss_out,
+                         double* gnorm2_out) {
+  if (!p || !R || !G_out) return MDD_EINVAL;
+  if (!p->kernel_set || !p->data_set || !p->full()) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  MDD_TRY(p->model_fft(R, nullptr, 0.0));
+  MDD_TRY(p->full_products());
+  TraceArgs a = p->blocked(p->F2(), p->d.nr);
+  a.x_out = G_out;
+  a.onset = p->mask_set ? p->onset() : nullptr;
+  a.part = p->gnp();
+  MDD_TRY(p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_GRAD, a, p->stream); }));
+  if (p->d.flags & MDD_FLAG_STORE_RF) {  // F still holds the spectra of R
+    p->spec_model = R;
+    p->spec_vel = nullptr;
+    p->spec_mu = 0.0;
+  }
+  return p->full_reduce(loss_out, gnorm2_out);
+}
+
+mdd_status mdd_full_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* opt,
+                         double* loss_out, double* gnorm2_out) {
+  if (!p || !R || !opt) return MDD_EINVAL;
+  if (!p->kernel_set || !p->data_set || !p->full()) return MDD_ESTATE;
+  TraceArgs a = p->blocked(p->F2(), p->d.nr);  // the update reads the summed gradient
+  int mode = 0;
+  MDD_TRY(update_args(*opt, s0, s1, a, mode));
+  const bool store = (p->d.flags & MDD_FLAG_STORE_RF) != 0;
+  const float* vel = mode == TM_NSGD ? s0 : nullptr;
+  const double mu = mode == TM_NSGD ? opt->mu : 0.0;
+  const bool have = store && p->spec_model == R && p->spec_vel == vel && p->spec_mu == mu;
+  p->spec_model = nullptr;
+  if (!have) MDD_TRY(p->model_fft(R, vel, mu));
+  MDD_TRY(p->full_products());
+  a.model = R;
+  a.store_spec = store ? 1 : 0;
+  a.onset = p->mask_set ? p->onset() : nullptr;
+  a.part = p->gnp();
+  MDD_TRY(p->run(MDD_KC_UPDATE, [&] { return launch_trace(mode, a, p->stream); }));
+  if (store) {  // the next point's spectra are where the gradient was: swap the buffers
+    p->fswap = !p->fswap;
+    p->spec_model = R;
+    p->spec_vel = vel;
+    p->spec_mu = mu;
+  }
+  return p->full_reduce(loss_out, gnorm2_out);
 }
 
 mdd_status mdd_invalidate_model_spectra(mdd_plan* p) {

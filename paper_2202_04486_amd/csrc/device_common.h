@@ -30,6 +30,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Deterministic block sum of one double per thread (blockDim.x == 256);
 // `red` is LDS of at least 4 doubles.  The result is valid in thread 0.
+// Adjoint-product output at element `off` of the spectra layout: written over R_k
+// in F (Gout NULL), or into Gout, or added to Gout (gacc: a sum over batches).
+template <class GemmArgsT>
+__device__ __forceinline__ void store_g(const GemmArgsT& a, long long off, float2 v) {
+  float2* p = (a.Gout ? a.Gout : a.F) + off;
+  if (a.gacc) v = cadd(v, *p);
+  *p = v;
+}
+
 __device__ __forceinline__ double block_sum256(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

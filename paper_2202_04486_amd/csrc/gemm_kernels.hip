@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
           float2* fw = a.F + rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+            if (rb + e < a.nr) store_g(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
         }
       }
     }
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
         float2* fw = a.F + (long long)rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+          if (rb + e < a.nr) store_g(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
       }
     }
   }
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const unsigned o = (unsigned)rb * rs32 + lr;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (rb + e < a.nr) base[o + (unsigned)e * rs32] = make_float2(re[e], im[e]);
+        if (rb + e < a.nr) store_g(a, (base - a.F) + o + (unsigned)e * rs32, make_float2(re[e], im[e]));
     }
     if (!has_next) break;
     __syncthreads();  // every wave is done with s_d, s_part, s_res of this item

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
           float2* fw = a.F + rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+            if (rb + e < a.nr) store_g(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
         }
       }
     }
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
       const int rb = mt * 16 + lq * 4;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (rb + e < a.nr) gbase[(long long)(rb + e) * rowstride] = make_float2(re[e], im[e]);
+        if (rb + e < a.nr) store_g(a, (gbase - a.F) + (long long)(rb + e) * rowstride, make_float2(re[e], im[e]));
     }
     if (!has_next) break;
     __syncthreads();  // every wave is done with s_d, s_part, s_r of this item
@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
         float2* fw = a.F + (long long)rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (rb + e < a.nr) fw[e * rowstride] = make_float2(re[e], im[e]);
+          if (rb + e < a.nr) store_g(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
       }
     }
   }

@@ -79,6 +79,8 @@ struct GemmArgs {
   const int32_t* idx;
   double* loss_part;      // [gridDim.x * gridDim.y]
   const float* dmax;      // [nf] largest |Re|, |Im| of D_k (fp16 split forms; else NULL)
+  float2* Gout;           // adjoint product destination (same layout as F); NULL: over R_k in F
+  int gacc;               // 1: add the adjoint product to Gout instead of writing it
   int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
 };
 
@@ -95,6 +97,7 @@ hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStre
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
                           hipStream_t s);
+hipError_t launch_iota(int32_t* out, int n, hipStream_t s);
 hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out,
                               hipStream_t s);
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,

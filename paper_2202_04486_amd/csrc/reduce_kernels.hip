@@ -149,6 +149,12 @@ __global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long
   if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
+// out[i] = i: the list of every source, batched in order by the full gradient.
+__global__ void k_iota(int32_t* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+
 }  // namespace
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
@@ -164,6 +170,11 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, s, out, n);
   return hipGetLastError();
 }
 

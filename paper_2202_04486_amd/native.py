@@ -14,13 +14,15 @@ MDD_OK, MDD_EINVAL, MDD_ESHAPE, MDD_ENOMEM, MDD_EHIP, MDD_EUNSUPPORTED, MDD_ESTA
     0, -1, -2, -3, -4, -5, -6
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3}
 FLAG_STORE_RF = 1
+FLAG_FULL_GRAD = 2
 OPT = {"sgd": 0, "adam": 1, "nsgd": 2}
 KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft")
 
 # Entry points the header declares (checked by the test-suite against the .so).
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
            "mdd_set_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward", "mdc_adjoint",
-           "mdd_stoch_grad", "mdd_step", "mdd_invalidate_model_spectra", "mdd_sigma_max2",
+           "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
+           "mdd_invalidate_model_spectra", "mdd_sigma_max2",
            "mdd_profile_enable", "mdd_profile_read", "mdd_status_string",
            "mdd_plan_last_hip_error")
 
@@ -70,6 +72,8 @@ def load() -> ctypes.CDLL:
         "mdc_adjoint": (_I32, [_P, _P, _P, _I32, _P]),
         "mdd_stoch_grad": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
         "mdd_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _I32, _P, _P]),
+        "mdd_full_grad": (_I32, [_P, _P, _P, _P, _P]),
+        "mdd_full_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _P]),
         "mdd_invalidate_model_spectra": (_I32, [_P]),
         "mdd_sigma_max2": (_I32, [_P, _I32, _P]),
         "mdd_profile_enable": (_I32, [_P, _I32, _I32]),

@@ -41,7 +41,7 @@ class Plan:
     'fp32', 'bf16x3', 'fp16x3', 'bf16'."""
 
     def __init__(self, ns, nr, nvs, nt, nf, nb_max, precision="fp32", store_rf=False,
-                 device=None):
+                 device=None, full_grad=False):
         self.lib = load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
@@ -49,7 +49,8 @@ class Plan:
         self.ns, self.nr, self.nvs, self.nt, self.nf, self.nb_max = ns, nr, nvs, nt, nf, nb_max
         self.precision = precision
         self.dims = make_dims(ns, nr, nvs, nt, nf, nb_max, precision,
-                              native.FLAG_STORE_RF if store_rf else 0)
+                              (native.FLAG_STORE_RF if store_rf else 0) |
+                              (native.FLAG_FULL_GRAD if full_grad else 0))
         nbytes = workspace_bytes(self.dims)
         if nbytes == 0:
             raise MddError("mdd_workspace_bytes", native.MDD_ESHAPE)
@@ -159,6 +160,32 @@ class Plan:
         loss_out = self._scalar(loss_out, "loss_out")
         gnorm2_out = self._scalar(gnorm2_out, "gnorm2_out")
         self._call("mdd_step", _ptr(R), _ptr(s0), _ptr(s1), ctypes.byref(o), _ptr(idx), nb,
+                   _ptr(loss_out), _ptr(gnorm2_out))
+        return loss_out, gnorm2_out
+
+    def mdd_full_grad(self, R, G_out=None, loss_out=None, gnorm2_out=None):
+        """Gradient of the whole finite-sum functional (every source; needs full_grad=True)."""
+        _need(R, "R", (self.nr, self.nvs, self.nt), torch.float32, self.device)
+        if G_out is None:
+            G_out = torch.empty_like(R)
+        _need(G_out, "G_out", (self.nr, self.nvs, self.nt), torch.float32, self.device)
+        loss_out = self._scalar(loss_out, "loss_out")
+        gnorm2_out = self._scalar(gnorm2_out, "gnorm2_out")
+        self._call("mdd_full_grad", _ptr(R), _ptr(G_out), _ptr(loss_out), _ptr(gnorm2_out))
+        return G_out, loss_out, gnorm2_out
+
+    def mdd_full_step(self, R, opt="sgd", lr=1e-2, s0=None, s1=None, t=1, beta1=0.9,
+                      beta2=0.999, eps=1e-8, mu=0.9, loss_out=None, gnorm2_out=None):
+        """One in-place full-gradient iteration (SGD: Landweber); returns (loss, gnorm2)."""
+        _need(R, "R", (self.nr, self.nvs, self.nt), torch.float32, self.device)
+        for name, st in (("s0", s0), ("s1", s1)):
+            if st is not None:
+                _need(st, name, (self.nr, self.nvs, self.nt), torch.float32, self.device)
+        o = Opt(native.OPT[opt], 0, float(lr), float(beta1), float(beta2), float(eps), float(mu),
+                int(t))
+        loss_out = self._scalar(loss_out, "loss_out")
+        gnorm2_out = self._scalar(gnorm2_out, "gnorm2_out")
+        self._call("mdd_full_step", _ptr(R), _ptr(s0), _ptr(s1), ctypes.byref(o),
                    _ptr(loss_out), _ptr(gnorm2_out))
         return loss_out, gnorm2_out
 

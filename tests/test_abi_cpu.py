@@ -54,9 +54,16 @@ def test_workspace_bytes_valid_and_monotone(lib):
     assert a > 0 and b > a and a % 256 == 0
 
 
+def test_full_gradient_flag_reserves_a_second_spectra_buffer(lib):
+    a = native.workspace_bytes(dims())
+    b = native.workspace_bytes(dims(flags=native.FLAG_FULL_GRAD))
+    spectra = 24 * 2 * 65 * 16 * 8          # nr x blocks of 16 columns x nf x 16 complex64
+    assert b - a >= spectra and (b - a) % 256 == 0
+
+
 @pytest.mark.parametrize("kw", [dict(nf=66), dict(nt=100), dict(nt=2048), dict(nb_max=33),
                                 dict(ns=100, nb_max=65), dict(ns=0), dict(nr=-1), dict(nf=0),
-                                dict(precision=7), dict(flags=2), dict(nvs=5000)])
+                                dict(precision=7), dict(flags=4), dict(nvs=5000)])
 def test_invalid_dims_rejected(lib, kw):
     assert native.workspace_bytes(dims(**kw)) == 0
     out = ctypes.c_void_p()
@@ -93,6 +100,8 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.mdc_adjoint(None, p, p, 1, p) == E
     assert lib.mdd_stoch_grad(None, p, p, 1, p, p, p) == E
     assert lib.mdd_step(None, p, p, p, ctypes.byref(opt), p, 1, p, p) == E
+    assert lib.mdd_full_grad(None, p, p, p, p) == E
+    assert lib.mdd_full_step(None, p, p, p, ctypes.byref(opt), p, p) == E
     assert lib.mdd_invalidate_model_spectra(None) == E
     assert lib.mdd_sigma_max2(None, 10, p) == E
     assert lib.mdd_profile_enable(None, 1, 10) == E
