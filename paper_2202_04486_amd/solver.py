@@ -9,6 +9,9 @@ per-step losses stay on the device until the epoch ends (one host sync per
 epoch).  The step size can be set from the largest singular value of the
 kernel (Appendix B): alpha = kappa * 2 / sigma_max^2, kappa = 0.4..0.6.
 
+FullGradientMDD is the full-gradient baseline (every source per iteration, e.g. the
+Landweber iteration) on the same kernels.
+
 Checkpoint / resume: `state_dict` captures the model, optimiser state, step
 counter, epoch / batch cursor and the permutation in use, so an interrupted
 epoch resumes on exactly the same batches.
@@ -150,3 +153,46 @@ class StochasticMDD:
     def load(self, path):
         with np.load(path, allow_pickle=False) as z:
             self.load_state_dict({k: z[k] for k in z.files})
+
+
+class FullGradientMDD:
+    """Full-gradient baseline the paper compares stochastic epochs with: every iteration
+    uses all sources (Theory section, the finite-sum functional; Appendix A, one full
+    iteration against one epoch).  With optimizer 'sgd' and lr = kappa * 2 / sigma_max^2
+    this is the Landweber iteration (Appendix B).  Needs a plan made with full_grad=True."""
+
+    def __init__(self, plan: Plan, optimizer: str = "sgd", lr: float | None = None,
+                 kappa: float = 0.5, mu: float = 0.9, R0: torch.Tensor | None = None,
+                 blowup: float = 1e6):
+        self.plan = plan
+        self.opt = optimizer
+        self.mu = mu
+        shape = (plan.nr, plan.nvs, plan.nt)
+        dev = plan.device
+        self.R = R0.clone() if R0 is not None else torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.s0 = torch.zeros(shape, dtype=torch.float32, device=dev) if optimizer != "sgd" else None
+        self.s1 = torch.zeros(shape, dtype=torch.float32, device=dev) if optimizer == "adam" else None
+        if lr is None:
+            lam = plan.mdd_sigma_max2(iters=100)
+            lr = kappa * 2.0 / float(lam.max().item())
+        self.lr = float(lr)
+        self.t = 0
+        self.blowup = blowup
+        self.loss0 = None
+        self.history = []
+
+    def run(self, iters: int):
+        """`iters` full iterations; returns their losses (taken before each update)."""
+        dev = self.plan.device
+        losses = torch.zeros(iters, dtype=torch.float64, device=dev)
+        for i in range(iters):
+            self.t += 1
+            self.plan.mdd_full_step(self.R, opt=self.opt, lr=self.lr, s0=self.s0, s1=self.s1,
+                                    t=self.t, mu=self.mu, loss_out=losses[i:i + 1])
+        out = losses.cpu().numpy()
+        if len(out):
+            if self.loss0 is None:
+                self.loss0 = float(out[0])
+            check_divergence(out, self.loss0, self.blowup)
+        self.history.extend(out.tolist())
+        return out

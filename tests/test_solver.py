@@ -105,3 +105,28 @@ def test_divergence_detected_on_gpu():
     with pytest.raises(solver.Diverged):
         for pm in synth.epoch_permutations(wl, 40):
             s.run_epoch(pm)
+
+
+@pytest.mark.gpu
+def test_full_gradient_solver_is_landweber():
+    """FullGradientMDD with the kernel-derived step (kappa 0.5: 1 / sigma_max^2) follows the
+    oracle's Landweber iteration on the tiny 2D workload and lowers the loss every step."""
+    from gpu_helpers import H, T, f32, relerr
+    from oracle import freq, optim
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["tiny2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u = f32(freq.mdc(d, f32(p["r_true"]), wl.nf))
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, 8, full_grad=True)
+    plan.mdd_set_kernel(T(d))
+    plan.mdd_set_data(T(u))
+    s = solver.FullGradientMDD(plan, optimizer="sgd", kappa=0.5)
+    s2, _ = stepsize.sigma_max2_kernel(d, wl.nf)
+    assert abs(s.lr - 1.0 / s2) <= 1e-4 * s.lr
+    losses = s.run(6)
+    ro = np.zeros((wl.nr, wl.nvs, wl.nt))
+    for _ in range(6):
+        ro = optim.sgd(ro, freq.batch_loss_grad(d, ro, u, np.arange(wl.ns), wl.nf)[1], s.lr)
+    assert relerr(H(s.R), ro) <= 1e-4
+    assert np.all(np.diff(losses) < 0)
