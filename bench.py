@@ -93,6 +93,32 @@ def step_tables(wl, nb, n_steps, dev):
     return torch.from_numpy(np.concatenate(tabs)).to(dev), np.concatenate(lens), spe
 
 
+def time_full_gradient(wl, d, u, onset_t, dev, iters, warmup=2):
+    """Milliseconds per full-gradient iteration (every source, SGD update, stored spectra):
+    the baseline a stochastic epoch is compared with (one pass over the data each)."""
+    import torch
+
+    from paper_2202_04486_amd.plan import Plan
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, store_rf=True, device=dev,
+                full_grad=True)
+    plan.mdd_set_kernel(d)
+    plan.mdd_set_data(u)
+    plan.mdd_set_mask(onset_t)
+    R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
+    loss = torch.zeros(warmup + iters, dtype=torch.float64, device=dev)
+    for j in range(warmup):
+        plan.mdd_full_step(R, opt="sgd", lr=1e-6, loss_out=loss[j:j + 1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(warmup, warmup + iters):
+        plan.mdd_full_step(R, opt="sgd", lr=1e-6, loss_out=loss[j:j + 1])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / iters
+    del plan
+    torch.cuda.empty_cache()
+    return ms
+
+
 def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2, store_rf=True):
     import torch
 
@@ -199,6 +225,8 @@ def main():
                     help="line2d (default, the headline) or the 1600-trace 3D patch")
     ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-gradient", action="store_true",
+                    help="skip timing the full-gradient iteration (every source per update)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-store-rf", action="store_true",
                     help="recompute the model spectra at each step instead of storing them")
@@ -322,6 +350,13 @@ def main():
                       "gemm_speedup_vs_fp32": per_launch(fp["prof"], "gemm") /
                       max(per_launch(res[f]["prof"], "gemm"), 1e-12)} for f in forms},
     }
+    if not args.no_full_gradient:
+        log("timing full-gradient iterations")
+        it_ms = time_full_gradient(wl, d, u, onset_t, dev, iters=5 if args.workload == "line2d" else 2)
+        out["full_gradient"] = {"iteration_ms": it_ms, "stochastic_epoch_ms": ms_step * spe,
+                                "epoch_over_iteration": ms_step * spe / it_ms,
+                                "note": "one full-gradient SGD (Landweber) iteration over all "
+                                        f"{wl.ns} sources in batches of {wl.nb}, fp32"}
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         cb, errs = cpu_baseline(wl, d, u, onset, R_eval, grads, idx0.cpu().numpy(), args.cpu_budget)
