@@ -9,9 +9,12 @@ sources at 10 m, 1024 samples at 4 ms, 257 retained bins, Ricker 15 Hz,
 8 periodic down-going events, 5 reflections, 20 dB noise, batches of 16, Adam,
 causality mask.  The FP32 form gives `value`; the bf16 and fp16 split forms
 are timed on the same data and reported beside it with their gradient error
-against the FP64 oracle.
+against the FP64 oracle.  `--workload patch3d` runs the 1600-trace 3D patch
+(40 x 40 grid at 25 m, 512 samples, 200 bins, batches of 64) instead.  One
+full-gradient iteration (every source, SGD) is timed beside the stochastic
+epoch.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload line2d|patch3d]
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """

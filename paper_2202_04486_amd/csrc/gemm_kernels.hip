@@ -6,11 +6,18 @@
 //   Res_k = D_{b,k} R_k - U_{b,k}      ([nb x nr] [nr x nvs])
 //   G_k   = D_{b,k}^H Res_k            ([nr x nb] [nb x nvs]), written over R_k
 //
-// A workgroup owns one frequency k and a group of TNB column blocks (16
-// virtual sources each).  Its batch rows of D_k are gathered by index into
-// LDS in receiver chunks (the whole receiver range when it fits: one global
-// round trip), the residual block stays in LDS between the
-// two products, and R_k is read and G_k written exactly once.
+// Kernels (the split-precision ones for more than 16 batch rows are in
+// gemm_split.hip):
+//   k_gemm<prec, NBT, TNB, kind>  tiled: a workgroup owns one frequency k and
+//       TNB column blocks (16 virtual sources each); the batch rows of D_k are
+//       gathered by index into LDS in receiver chunks and the residual block
+//       stays in LDS between the two products.  Every kind and precision.
+//   k_gemm_pipe   fp32, fused, nb <= 16, nr <= PIPE_KC: persistent, the next
+//       item's R_k in flight during the current item's products.
+//   k_gemm_ws     fp32, fused, 33 <= nb <= 64: loader waves stream R_k through
+//       an LDS ring for the compute waves; the adjoint needs no barrier.
+// R_k is read and G_k written exactly once.  G_k goes over R_k, or (the full
+// gradient) into, or added to, a second spectra buffer.
 //
 // There is no complex MFMA: a complex product is four real products
 // (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br) on v_mfma_f32_16x16x4_f32, or, in

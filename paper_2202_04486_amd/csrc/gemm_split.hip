@@ -1,4 +1,7 @@
-// Split-precision per-frequency products for batches of 17..64 sources.
+// Split-precision (bf16x3, fp16x3) per-frequency products:
+//   k_gemm_spipe     fused kind, nb <= 16: persistent, like the fp32 k_gemm_pipe;
+//   k_gemm_split     tiled, every kind, 16 < nb <= 64 (the fused kind up to 32);
+//   k_gemm_split_ws  fused kind, 33 <= nb <= 64: warp-specialised.
 //
 // Same operation as the float32 kernels (Theory section, matrix form of the
 // MDC operator per frequency): the forward product D_{b,k} R_k with the
@@ -725,14 +728,14 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 33..64 batch rows, fused kind: a warp-specialised workgroup of eight waves.
-// Waves 0-3 compute with the same LDS planes and MFMA tiling as the kernel
-// above (each owns one 16-column tile and all four row tiles).  Waves 4-7 only
-// stream R_k: they keep WS_DEPTH 64-receiver chunks in flight in their
-// registers and hand each to the compute waves through a two-slot LDS ring of
-// float32 values.  D_{b,k} chunks are double-buffered as well, so a single
-// barrier separates consecutive chunks.  (With one role per wave, each wave
-// has one chunk in flight and waits on memory for about half of its time.)
+// 33..64 batch rows, fused kind: a warp-specialised workgroup of twelve waves.
+// Eight compute waves use the same LDS planes and 16x16x32 tiling as the tiled
+// kernel (each owns one 16-column tile and two of the four row tiles).  Four
+// loader waves only stream R_k: they keep WS_DEPTH 64-receiver chunks in flight
+// in their registers and hand each to the compute waves through a two-slot LDS
+// ring of float32 values.  D_{b,k} chunks are double-buffered as well, so a
+// single barrier separates consecutive chunks.  (With one role per wave, each
+// wave has one chunk in flight and waits on memory for about half of its time.)
 constexpr int WS_DEPTH = 3;
 constexpr int WS_CW = 8;                   // compute waves (two per SIMD)
 constexpr int WS_LW = 4;                   // loader waves
@@ -864,8 +867,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
 
   // ---- compute side: D chunks for the forward product ([b][r] planes)
   // D loads are unconditional too (a rejected index reads row 0 of the frequency,
-  // a receiver beyond nr reads receiver 0); staging zeroes them.  Only the fp16
-  // form looks at the values when they arrive (its per-chunk scale).
+  // a receiver beyond nr reads receiver 0); staging zeroes them.
   const long long drow0 = (long long)k * a.ns * a.nrp;
   auto d_at = [&](int b, int r) -> long long {
     const long long off = s_drow[b];

@@ -8,9 +8,10 @@
 // spectrum), with a radix-8 Stockham FFT held in registers: each lane owns 8
 // points n = j + L r (L = N2/8 lanes per trace, r < 8), passes exchange data
 // through a wave-private LDS region.  A workgroup owns one tile of 16 traces
-// whose spectra form one contiguous [nf][16] block in HBM, staged in LDS so
-// both the time side (whole traces) and the frequency side (whole blocks) are
-// read and written with contiguous accesses.
+// (half of one in the gradient and update modes of long traces) whose spectra
+// form one contiguous [nf][16] block in HBM, staged in LDS so both the time
+// side (whole traces) and the frequency side (whole blocks) are read and
+// written with contiguous accesses.
 #include "device_common.h"
 #include "mdd_internal.h"
 
