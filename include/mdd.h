@@ -187,6 +187,15 @@ mdd_status mdd_full_grad(mdd_plan* plan, const float* R, float* G_out, double* l
 mdd_status mdd_full_step(mdd_plan* plan, float* R, float* s0, float* s1, const mdd_opt* opt,
                          double* loss_out, double* gnorm2_out);
 
+/* Reciprocity preconditioner C_r (Theory section): out = (z + z^T) / 2, the
+ * transpose swapping the first two axes of z [n][n][nt] float32 (receivers and
+ * virtual sources, which then coincide).  C_r is self-adjoint, so the same call
+ * is its adjoint.  z and out are device pointers, 16-byte aligned; out may be z
+ * (in place), otherwise the two must not overlap.  No plan: enqueued on `stream`.
+ * Errors: EINVAL (NULL or misaligned), ESHAPE (n outside [1, 4096], nt not one of
+ * 128, 256, 512, 1024), EHIP. */
+mdd_status mdd_reciprocity(const float* z, float* out, int32_t n, int32_t nt, void* stream);
+
 /* Forget stored model spectra (MDD_FLAG_STORE_RF): call after changing R
  * other than through mdd_step. */
 mdd_status mdd_invalidate_model_spectra(mdd_plan* plan);

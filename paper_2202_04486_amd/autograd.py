@@ -4,14 +4,18 @@ U_b = P+_b R (time in, time out; Theory section, the operator of the
 time-domain functional, applied as transform / per-frequency product /
 inverse transform as in Appendix A) runs in `mdc_forward`; its backward is the
 hand-written adjoint kernel `mdc_adjoint`, so any loss built in torch on U_b
-(and any preconditioner applied in torch before it, e.g. reciprocity
-(z + z^T)/2) differentiates through the library.  Only the batch indices are
+(and the reciprocity preconditioner C_r below, or any preconditioner applied
+in torch before it) differentiates through the library.  Only the batch indices are
 saved for backward: the operator is linear in R, so neither R nor its spectra
 are kept between forward and backward.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
+
+from . import native
 
 from .plan import Plan
 
@@ -37,7 +41,33 @@ def mdc(R: torch.Tensor, idx: torch.Tensor, plan: Plan) -> torch.Tensor:
     return MDC.apply(R, idx, plan)
 
 
+class Reciprocity(torch.autograd.Function):
+    """C_r z = (z + z^T)/2 over (receiver, virtual source) by the library's kernel
+    (mdd_reciprocity); C_r is self-adjoint, so its backward is the same kernel."""
+
+    @staticmethod
+    def forward(ctx, z: torch.Tensor):
+        return _reciprocity(z)
+
+    @staticmethod
+    def backward(ctx, grad: torch.Tensor):
+        return _reciprocity(grad)
+
+
+def _reciprocity(z: torch.Tensor) -> torch.Tensor:
+    if z.dim() != 3 or z.shape[0] != z.shape[1] or z.dtype != torch.float32 or not z.is_cuda:
+        raise ValueError("reciprocity needs a float32 CUDA tensor [n][n][nt]")
+    z = z.contiguous()
+    out = torch.empty_like(z)
+    lib = native.load()
+    stream = torch.cuda.current_stream(z.device).cuda_stream
+    native.check("mdd_reciprocity", lib.mdd_reciprocity(
+        ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(out.data_ptr()), z.shape[0], z.shape[2],
+        ctypes.c_void_p(stream)))
+    return out
+
+
 def reciprocity(z: torch.Tensor) -> torch.Tensor:
     """Reciprocity preconditioner C_r z = (z + z^T)/2 over (receiver, virtual source),
     in-graph (Theory section, preconditioned functional); self-adjoint."""
-    return 0.5 * (z + z.transpose(0, 1))
+    return Reciprocity.apply(z)

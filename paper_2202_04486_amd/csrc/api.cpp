@@ -2,6 +2,7 @@
 // (always before any HIP call), the workspace layout, and the sequence of
 // kernel launches for each entry point on the plan's stream.
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <new>
 #include <vector>
@@ -501,6 +502,15 @@ mdd_status mdd_full_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_
     p->spec_mu = mu;
   }
   return p->full_reduce(loss_out, gnorm2_out);
+}
+
+mdd_status mdd_reciprocity(const float* z, float* out, int32_t n, int32_t nt, void* stream) {
+  if (!z || !out) return MDD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(out)) & 15) return MDD_EINVAL;
+  if (n < 1 || n > MAX_EXTENT || !valid_nt(nt)) return MDD_ESHAPE;
+  return launch_reciprocity(z, out, n, nt, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? MDD_OK
+             : MDD_EHIP;
 }
 
 mdd_status mdd_invalidate_model_spectra(mdd_plan* p) {

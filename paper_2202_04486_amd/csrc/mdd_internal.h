@@ -98,6 +98,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
                           hipStream_t s);
 hipError_t launch_iota(int32_t* out, int n, hipStream_t s);
+hipError_t launch_reciprocity(const float* z, float* out, int n, int nt, hipStream_t s);
 hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out,
                               hipStream_t s);
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,

@@ -1,7 +1,8 @@
-// Float64 reductions (loss, gradient norm, out-of-band data energy) and the
-// per-frequency power iteration for the largest singular value of the kernel.
-// Every sum runs in a fixed order (no atomics), so results are bitwise
-// reproducible run to run.
+// Float64 reductions (loss, gradient norm, out-of-band data energy), the
+// per-frequency power iteration for the largest singular value of the kernel, and
+// the small helpers: the reciprocity average (z + z^T) / 2, per-frequency maxima of
+// D_k, the list of every source.  Every sum runs in a fixed order (no atomics), so
+// results are bitwise reproducible run to run.
 #include "device_common.h"
 #include "mdd_internal.h"
 
@@ -149,6 +150,23 @@ __global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long
   if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
+// C_r z = (z + z^T) / 2 over the first two axes of [n][n][nt]: the workgroup of
+// pair (r, vs), r <= vs, reads both traces and writes the average to both, so the
+// call may run in place.
+__global__ __launch_bounds__(256) void k_reciprocity(const float* z, float* out, int n, int nt) {
+  const int vs = blockIdx.x, r = blockIdx.y;
+  if (vs < r) return;
+  const long long ta = ((long long)r * n + vs) * nt, tb = ((long long)vs * n + r) * nt;
+  for (int i = threadIdx.x * 4; i < nt; i += 256 * 4) {
+    const float4 a = *reinterpret_cast<const float4*>(z + ta + i);
+    const float4 b = *reinterpret_cast<const float4*>(z + tb + i);
+    const float4 m = make_float4((a.x + b.x) * 0.5f, (a.y + b.y) * 0.5f, (a.z + b.z) * 0.5f,
+                                 (a.w + b.w) * 0.5f);
+    *reinterpret_cast<float4*>(out + ta + i) = m;
+    *reinterpret_cast<float4*>(out + tb + i) = m;
+  }
+}
+
 // out[i] = i: the list of every source, batched in order by the full gradient.
 __global__ void k_iota(int32_t* out, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -170,6 +188,11 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reciprocity(const float* z, float* out, int n, int nt, hipStream_t s) {
+  hipLaunchKernelGGL(k_reciprocity, dim3(n, n), dim3(256), 0, s, z, out, n, nt);
   return hipGetLastError();
 }
 

@@ -134,3 +134,43 @@ def test_patch3d_gradient_sampled_columns(patch3d, prec, tol):
     del G
     plan.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,nt", [(1, 128), (7, 256), (37, 512), (301, 1024)])
+def test_reciprocity_kernel(n, nt):
+    """mdd_reciprocity: bit-exact against (z + z^T) * 0.5 in float32 (one addition and an
+    exact halving), out of place and in place, and within rounding of the FP64 oracle."""
+    import ctypes
+    from paper_2202_04486_amd import native
+    z0 = np.random.default_rng(n).standard_normal((n, n, nt)).astype(np.float32)
+    want = (z0 + z0.transpose(1, 0, 2)) * np.float32(0.5)      # float32 arithmetic
+    assert want.dtype == np.float32
+    z = T(z0)
+    out = torch.full_like(z, float("nan"))
+    lib = native.load()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    native.check("mdd_reciprocity", lib.mdd_reciprocity(ctypes.c_void_p(z.data_ptr()),
+                                                        ctypes.c_void_p(out.data_ptr()), n, nt, s))
+    torch.cuda.synchronize()
+    assert np.array_equal(H(out).astype(np.float32), want)
+    assert np.array_equal(H(z).astype(np.float32), z0)
+    native.check("mdd_reciprocity", lib.mdd_reciprocity(ctypes.c_void_p(z.data_ptr()),
+                                                        ctypes.c_void_p(z.data_ptr()), n, nt, s))
+    torch.cuda.synchronize()
+    assert np.array_equal(H(z).astype(np.float32), want)
+    assert relerr(H(out), optim.reciprocity(z0.astype(np.float64))) <= 1e-7
+
+
+def test_reciprocity_kernel_rejects_bad_arguments():
+    import ctypes
+    from paper_2202_04486_amd import native
+    lib = native.load()
+    z = torch.zeros(4, 4, 128, device="cuda")
+    p = ctypes.c_void_p(z.data_ptr())
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    codes = [lib.mdd_reciprocity(None, p, 4, 128, s),
+             lib.mdd_reciprocity(ctypes.c_void_p(z.data_ptr() + 4), p, 4, 128, s),
+             lib.mdd_reciprocity(p, p, 0, 128, s),
+             lib.mdd_reciprocity(p, p, 4097, 128, s),
+             lib.mdd_reciprocity(p, p, 4, 200, s)]
+    assert codes == [native.MDD_EINVAL] * 2 + [native.MDD_ESHAPE] * 3
