@@ -10,11 +10,14 @@ sources at 10 m, 1024 samples at 4 ms, 257 retained bins, Ricker 15 Hz,
 causality mask.  The FP32 form gives `value`; the bf16 and fp16 split forms
 are timed on the same data and reported beside it with their gradient error
 against the FP64 oracle.  `--workload patch3d` runs the 1600-trace 3D patch
-(40 x 40 grid at 25 m, 512 samples, 200 bins, batches of 64) instead.  One
-full-gradient iteration (every source, SGD) is timed beside the stochastic
-epoch.
+(40 x 40 grid at 25 m, 512 samples, 200 bins, batches of 64) instead;
+`line2d_vs1` and `patch3d_vs1` invert for one virtual source in the middle of
+the line (batches of 32, Nesterov momentum) or of the patch (batches of 64,
+Adam), where the products are matrix-vector products.  One full-gradient
+iteration (every source, SGD) is timed beside the stochastic epoch.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload line2d|patch3d]
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+                    [--workload line2d|patch3d|line2d_vs1|patch3d_vs1]
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -39,7 +42,16 @@ WORKLOAD_TEXT = {
               "causality mask, 20 dB noise, stored model spectra",
     "patch3d": "patch3d: ns=nr=nvs=1600 (40x40 grid at 25 m), nt=512 (4 ms), nf=200, batch 64, "
                "Adam, causality mask, noise-free, stored model spectra",
+    "line2d_vs1": "line2d_vs1: ns=nr=201 (10 m line), one virtual source at receiver 100, "
+                  "nt=1024 (4 ms), nf=257, batch 32, Nesterov momentum 0.9 at the kernel-derived "
+                  "step, causality mask, 20 dB noise, stored model spectra",
+    "patch3d_vs1": "patch3d_vs1: ns=nr=1600 (40x40 grid at 25 m), one virtual source at grid "
+                   "point (20, 20), nt=512 (4 ms), nf=200, batch 64, Adam, causality mask, "
+                   "noise-free, stored model spectra",
 }
+DEFAULT_EPOCHS = {"line2d": 10, "patch3d": 1, "line2d_vs1": 50, "patch3d_vs1": 10}
+# Model-sized float32 arrays each update reads and writes (R and the optimiser state).
+STATE_ARRAYS = {"adam": 3, "nsgd": 2, "sgd": 1}
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
 TRAFFIC_FILE = {w: os.path.join(ROOT, "profiles", f"traffic_{w}.md") for w in WORKLOAD_TEXT}
@@ -56,7 +68,7 @@ def make_inputs(wl, dev):
 
     import synth
     g = synth.streams(wl.seed)
-    xs, xr, xv = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl), synth.positions(wl.nvs, wl)
+    xs, xr, xv = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl), synth.vs_positions(wl)
     d = synth.cube_on_device(xs, xr, wl, synth.down_events(wl, g[0]), dev)
     r_true = synth.cube_on_device(xr, xv, wl, synth.reflection_events(wl, g[1]), dev)
     noise = None
@@ -123,6 +135,8 @@ def time_full_gradient(wl, d, u, onset_t, dev, iters, warmup=2):
 
 
 def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2, store_rf=True):
+    """Adam at lr, or Nesterov momentum (mu 0.9) at half the kernel-derived step
+    2 / sigma_max^2 (Appendix B), as the workload states."""
     import torch
 
     from paper_2202_04486_amd.plan import Plan
@@ -131,13 +145,16 @@ def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2
     plan.mdd_set_kernel(d)
     plan.mdd_set_data(u)
     plan.mdd_set_mask(onset_t)
+    opt = wl.optimizer
+    if opt == "nsgd":
+        lr = 0.5 * 2.0 / float(plan.mdd_sigma_max2(iters=100).max().item())
     R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
     m, v = torch.zeros_like(R), torch.zeros_like(R)
     loss = torch.zeros(warmup + steps, dtype=torch.float64, device=dev)
     gn = torch.zeros_like(loss)
 
     def step(j):
-        plan.mdd_step(R, idx_tab[j, :lens[j]], opt="adam", lr=lr, s0=m, s1=v, t=j + 1,
+        plan.mdd_step(R, idx_tab[j, :lens[j]], opt=opt, lr=lr, s0=m, s1=v, t=j + 1, mu=0.9,
                       loss_out=loss[j:j + 1], gnorm2_out=gn[j:j + 1])
 
     for j in range(warmup):
@@ -224,8 +241,9 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 10 epochs of line2d, 1 epoch of patch3d)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="line2d", choices=["line2d", "patch3d"],
-                    help="line2d (default, the headline) or the 1600-trace 3D patch")
+    ap.add_argument("--workload", default="line2d", choices=list(WORKLOAD_TEXT),
+                    help="line2d (default, the headline), the 1600-trace 3D patch, or either "
+                         "with a single virtual source")
     ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-gradient", action="store_true",
@@ -246,9 +264,9 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     spe0 = math.ceil(wl.ns / wl.nb)
     if args.steps is None:
-        args.steps = 10 * spe0 if args.workload == "line2d" else spe0
+        args.steps = DEFAULT_EPOCHS[args.workload] * spe0
     if args.warmup is None:
-        args.warmup = spe0 if args.workload == "line2d" else 5
+        args.warmup = spe0 if wl.grid == "line" else 5
     if args.workload != "line2d":
         args.no_cpu_baseline = True      # the oracle's full gradient at this size takes minutes
     dev = torch.device("cuda", 0)
@@ -274,6 +292,9 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     if "fp32" not in forms:
         forms.insert(0, "fp32")
+    vs1 = wl.nvs == 1
+    if vs1:
+        forms = ["fp32"]  # one virtual source: every precision setting runs the float32 kernel
     res, grads = {}, {}
     idx0 = idx_tab[0, :lens[0]]
     R_eval = None
@@ -305,10 +326,20 @@ def main():
     cls_ms = {k: per_launch(fp["prof"], k) for k in fp["prof"]}
     dominant = max(cls_ms, key=lambda k: cls_ms[k] * fp["prof"][k][1])
     upd_ms = cls_ms["update"]
-    upd_bytes = 24.0 * Mt                      # R, m, v read and written (float32)
+    upd_bytes = 8.0 * STATE_ARRAYS[wl.optimizer] * Mt   # R and its state, read and written
     traffic = stored_traffic(args.workload, "update")
     gemm_flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
-    if dominant == "gemm":
+    # One virtual source: D_b read once, U_b, the model spectra in and the gradient out.
+    gemv_bytes = 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * wl.nf + 2 * 8.0 * wl.nr * wl.nf
+    if dominant == "gemm" and vs1:
+        gm_ms = cls_ms["gemm"]
+        roofline = {"kernel": "gemv (one pass over D_b: forward product + residual + loss + "
+                              "adjoint product)", "bound": "hbm",
+                    "achieved": gemv_bytes / (gm_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "traffic": stored_traffic(args.workload, "gemv"),
+                    "traffic_unit": "HBM bytes per launch (counters)",
+                    "algorithmic_bytes": gemv_bytes}
+    elif dominant == "gemm":
         gm_ms = cls_ms["gemm"]
         roofline = {"kernel": "gemm (forward product + residual + loss + adjoint product)",
                     "bound": "mfma", "achieved": gemm_flops / (gm_ms * 1e-3) / 1e12,
@@ -317,7 +348,8 @@ def main():
                     "traffic_unit": "HBM bytes per launch (counters)",
                     "algorithmic_flops": gemm_flops}
     else:
-        roofline = {"kernel": "update (inverse FFT + mask + Adam + model FFT)", "bound": "hbm",
+        roofline = {"kernel": f"update (inverse FFT + mask + {wl.optimizer} + model FFT)",
+                    "bound": "hbm",
                     "achieved": upd_bytes / (upd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (counters)",
@@ -326,6 +358,13 @@ def main():
 
     def gemm_roof(form):
         ms = per_launch(res[form]["prof"], "gemm")
+        if vs1:
+            tr = stored_traffic(args.workload, "gemv")
+            return {"ms": ms, "bound": "hbm", "algorithmic_bytes": gemv_bytes,
+                    "achieved_gbs": gemv_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "frac": gemv_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
+                    "traffic": tr, "hbm_gbs": (tr / (ms * 1e-3) / 1e9) if tr else None}
         hw = gemm_flops * (3 if form in ("bf16x3", "fp16x3") else 1)
         tr = stored_traffic(args.workload, f"gemm_{form}")
         return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
@@ -333,7 +372,7 @@ def main():
                 "frac": hw / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[form],
                 "traffic": tr, "hbm_gbs": (tr / (ms * 1e-3) / 1e9) if tr else None}
 
-    alg_bytes = 24.0 * Mt + 2 * 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * wl.nvs * wl.nf
+    alg_bytes = upd_bytes + (1 if vs1 else 2) * 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * wl.nvs * wl.nf
     out = {
         "metric": METRIC, "value": value, "unit": "grad evals/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

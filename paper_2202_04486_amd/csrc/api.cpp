@@ -20,7 +20,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 bool valid_nt(int nt) { return nt == 128 || nt == 256 || nt == 512 || nt == 1024; }
 
 struct Layout {
-  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, red2, f2, sidx, lossb, total;
+  size_t tw, df, uf, oob, oobp, onset, f, bsp, lossp, gnp, dmx, red2, f2, sidx, lossb, gvp, total;
 };
 
 Layout make_layout(const mdd_dims& d) {
@@ -41,7 +41,9 @@ Layout make_layout(const mdd_dims& d) {
   L.onset = take(sizeof(int32_t) * d.nr * d.nvs);
   L.f = take(c8 * d.nr * nvb * d.nf * CB);
   L.bsp = take(c8 * d.nb_max * nvb * d.nf * CB);
-  L.lossp = take(sizeof(double) * d.nf * nvb);
+  // nvs = 1: the matrix-vector products write one loss partial per row group.
+  const size_t ngv = d.nvs == 1 ? gemv_groups(d.nb_max, d.nf) : 0;
+  L.lossp = take(sizeof(double) * d.nf * (ngv > nvb ? ngv : nvb));
   L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
   L.dmx = take(sizeof(float) * d.nf);               // per-frequency max |D| (fp16 scaling)
   L.red2 = take(sizeof(double) * 512);              // two-level reduction stage
@@ -49,6 +51,7 @@ Layout make_layout(const mdd_dims& d) {
   L.f2 = take(full ? c8 * d.nr * nvb * d.nf * CB : 0);
   L.sidx = take(full ? sizeof(int32_t) * d.ns : 0);
   L.lossb = take(full ? sizeof(double) * ((d.ns + d.nb_max - 1) / d.nb_max) : 0);
+  L.gvp = take(ngv > 1 ? sizeof(float4) * d.nf * ngv * (nrp / 2) : 0);  // row-group partials
   L.total = o;
   return L;
 }
@@ -110,7 +113,16 @@ struct mdd_plan {
   double* red2() const { return at<double>(L.red2); }
   int32_t* sidx() const { return at<int32_t>(L.sidx); }
   double* lossb() const { return at<double>(L.lossb); }
+  float4* gvp() const { return at<float4>(L.gvp); }
   bool full() const { return (d.flags & MDD_FLAG_FULL_GRAD) != 0; }
+  // One virtual source: the time arrays [rows][1][nt] are handled as one row of `rows`
+  // columns, so spectra blocks hold 16 receivers (or batch rows), and the products are
+  // matrix-vector products.
+  bool vs1() const { return d.nvs == 1; }
+  // Float64 partials of ||g||^2 written by the gradient / update kernels.
+  int n_gn() const { return (vs1() ? nblocks(d.nr) : d.nr * nvb) * trace_update_split(d.nt); }
+  // Float64 loss partials written by one fused product launch over a batch of nb.
+  int n_loss(int nb) const { return d.nf * (vs1() ? gemv_groups(nb, d.nf) : gemm_ncg(nb, nvb)); }
 
   template <class Fn>
   mdd_status run(int kclass, Fn&& fn) {
@@ -139,11 +151,11 @@ struct mdd_plan {
     TraceArgs a{};
     a.nt = d.nt;
     a.nf = d.nf;
-    a.rows = rows;
-    a.ncols = d.nvs;
-    a.ncb = nvb;
+    a.rows = vs1() ? 1 : rows;
+    a.ncols = vs1() ? rows : d.nvs;
+    a.ncb = vs1() ? nblocks(rows) : nvb;
     a.spec = spec;
-    a.s_row = (long long)nvb * d.nf * CB;
+    a.s_row = (long long)a.ncb * d.nf * CB;
     a.s_cb = (long long)d.nf * CB;
     a.s_k = CB;
     a.tw = tw();
@@ -168,7 +180,18 @@ struct mdd_plan {
     g.nf = d.nf;
     g.nt = d.nt;
     g.nb = nb;
+    if (vs1()) {
+      g.P = gemv_groups(nb, d.nf);
+      g.gpart = gvp();
+    }
     return g;
+  }
+
+  // Per-frequency products of one batch (any kind) on the plan's stream.
+  mdd_status products(int kind, const GemmArgs& g) {
+    return run(MDD_KC_GEMM, [&] {
+      return vs1() ? launch_gemv(kind, g, stream) : launch_gemm(kind, d.precision, g, stream);
+    });
   }
 
   mdd_status model_fft(const float* R, const float* vel, double mu) {
@@ -184,14 +207,14 @@ struct mdd_plan {
     if (!loss_out && !gnorm2_out) return MDD_OK;
     ReduceArgs r{};
     r.loss_part = lossp();
-    r.n_loss = with_loss ? d.nf * gemm_ncg(nb, nvb) : 0;
+    r.n_loss = with_loss ? n_loss(nb) : 0;
     r.loss_scale = 1.0 / (2.0 * d.nt);
     r.oob = with_loss ? oob() : nullptr;
     r.idx = idx;
     r.nb = nb;
     r.ns = d.ns;
     r.gn_part = gnp();
-    r.n_gn = gnorm2_out ? d.nr * nvb * trace_update_split(d.nt) : 0;
+    r.n_gn = gnorm2_out ? n_gn() : 0;
     r.loss_out = loss_out;
     r.gnorm2_out = gnorm2_out;
     r.stage = red2();
@@ -208,7 +231,7 @@ struct mdd_plan {
       GemmArgs g = gemm(idx, nb);
       g.Gout = F2();
       g.gacc = j > 0 ? 1 : 0;
-      mdd_status st = run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, d.precision, g, stream); });
+      mdd_status st = products(GK_FUSED, g);
       if (st != MDD_OK) return st;
       st = reduce(idx, nb, true, lossb() + j, nullptr);
       if (st != MDD_OK) return st;
@@ -228,7 +251,7 @@ struct mdd_plan {
     r.nb = 0;
     r.ns = d.ns;
     r.gn_part = gnp();
-    r.n_gn = d.nr * nvb * trace_update_split(d.nt);
+    r.n_gn = n_gn();
     r.loss_out = loss_out;
     r.gnorm2_out = gnorm2_out;
     r.stage = red2();
@@ -389,7 +412,7 @@ mdd_status mdc_forward(mdd_plan* p, const float* R, const int32_t* idx, int32_t 
   p->spec_model = nullptr;
   MDD_TRY(p->model_fft(R, nullptr, 0.0));
   const GemmArgs g = p->gemm(idx, nb);
-  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FWD, p->d.precision, g, p->stream); }));
+  MDD_TRY(p->products(GK_FWD, g));
   TraceArgs a = p->blocked(p->Bsp(), nb);
   a.x_out = U_out;
   return p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_IRFFT, a, p->stream); });
@@ -404,7 +427,7 @@ mdd_status mdc_adjoint(mdd_plan* p, const float* V, const int32_t* idx, int32_t 
   a.x_in = V;
   MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
   const GemmArgs g = p->gemm(idx, nb);
-  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_ADJ, p->d.precision, g, p->stream); }));
+  MDD_TRY(p->products(GK_ADJ, g));
   TraceArgs b = p->blocked(p->F(), p->d.nr);
   b.x_out = G_out;
   return p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_IRFFT, b, p->stream); });
@@ -418,7 +441,7 @@ mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32
   p->spec_model = nullptr;
   MDD_TRY(p->model_fft(R, nullptr, 0.0));
   const GemmArgs g = p->gemm(idx, nb);
-  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, p->d.precision, g, p->stream); }));
+  MDD_TRY(p->products(GK_FUSED, g));
   TraceArgs a = p->blocked(p->F(), p->d.nr);
   a.x_out = G_out;
   a.onset = p->mask_set ? p->onset() : nullptr;
@@ -442,7 +465,7 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
   p->spec_model = nullptr;
   if (!have) MDD_TRY(p->model_fft(R, vel, mu));
   const GemmArgs g = p->gemm(idx, nb);
-  MDD_TRY(p->run(MDD_KC_GEMM, [&] { return launch_gemm(GK_FUSED, p->d.precision, g, p->stream); }));
+  MDD_TRY(p->products(GK_FUSED, g));
   a.model = R;
   a.store_spec = store ? 1 : 0;
   a.onset = p->mask_set ? p->onset() : nullptr;

@@ -82,6 +82,10 @@ struct GemmArgs {
   float2* Gout;           // adjoint product destination (same layout as F); NULL: over R_k in F
   int gacc;               // 1: add the adjoint product to Gout instead of writing it
   int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
+  // Single virtual source (launch_gemv): row groups per frequency and their adjoint
+  // partials [nf][P][nrp / 2] (receiver pairs).
+  int P;
+  float4* gpart;
 };
 
 hipError_t launch_twiddles(float2* tw, int nt, hipStream_t s);
@@ -94,6 +98,11 @@ hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s
 // at nb <= 16 over at most SPLIT_PIPE_KC receivers (persistent kernel).
 constexpr int SPLIT_PIPE_KC = 256;
 hipError_t launch_gemm_split(int kind, int precision, const GemmArgs& a, hipStream_t s);
+// nvs = 1 products (gemv_kernels.hip): every kind, every precision, in float32; spectra
+// in the one-row layout.  a.P = gemv_groups(nb, nf) row groups per frequency; with P > 1
+// the adjoint kinds take a second launch that adds the group partials.
+int gemv_groups(int nb, int nf);
+hipError_t launch_gemv(int kind, const GemmArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, double* out,
                           hipStream_t s);

@@ -53,6 +53,7 @@ class Workload:
     mask: bool
     seed: int
     nb_sweep: tuple = field(default_factory=tuple)
+    vs_first: int = 0    # receiver position of the first virtual source
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -75,6 +76,14 @@ WORKLOADS = {
     "patch3d": Workload("patch3d", 1600, 1600, 1600, 512, 0.004, 200, 25.0, "patch", 40, 12.0,
                         "periodic", 10, (0.05, 0.2), (0.1, 0.15), 5, (0.05, 0.5),
                         None, 64, "adam", 20, True, 0),
+    # Single virtual source in the middle of the 2D line (receiver 100), batches of 32.
+    "line2d_vs1": Workload("line2d_vs1", 201, 201, 1, 1024, 0.004, 257, 10.0, "line", 0, 15.0,
+                           "periodic", 8, (0.05, 0.3), (0.2, 0.3), 5, (0.1, 0.8),
+                           20.0, 32, "nsgd", 20, True, 0, vs_first=100),
+    # Single virtual source in the middle of the 3D patch (grid point (20, 20)).
+    "patch3d_vs1": Workload("patch3d_vs1", 1600, 1600, 1, 512, 0.004, 200, 25.0, "patch", 40,
+                            12.0, "periodic", 10, (0.05, 0.2), (0.1, 0.15), 5, (0.05, 0.5),
+                            None, 64, "adam", 20, True, 0, vs_first=820),
 }
 
 
@@ -100,6 +109,12 @@ def ricker(tau, f0: float, xp=np):
 
 def _signed_amplitudes(rng, n):
     return rng.choice([-1.0, 1.0], size=n) * rng.uniform(0.5, 1.0, size=n)
+
+
+def vs_positions(wl: Workload, nvs=None) -> np.ndarray:
+    """Virtual-source coordinates: receiver positions vs_first .. vs_first + nvs - 1."""
+    nvs = nvs or wl.nvs
+    return positions(wl.vs_first + nvs, wl)[wl.vs_first:]
 
 
 def down_events(wl: Workload, rng=None) -> dict:
@@ -166,7 +181,7 @@ def onsets(wl: Workload, nr=None, nvs=None) -> np.ndarray:
     direct-arrival time |x_r - x_vs| / V_MASK minus 1.5 Ricker periods."""
     nr = nr or wl.nr
     nvs = nvs or wl.nvs
-    xr, xv = positions(nr, wl), positions(nvs, wl)
+    xr, xv = positions(nr, wl), vs_positions(wl, nvs)
     h = np.sqrt(((xr[:, None, :] - xv[None, :, :]) ** 2).sum(-1))
     on = np.ceil((h / V_MASK - 1.5 / wl.f0) / wl.dt)
     return np.maximum(on, 0).astype(np.int32)
@@ -176,7 +191,7 @@ def make_problem(wl: Workload, with_noise: bool = True) -> dict:
     """FP64 host arrays: d [ns][nr][nt], r_true [nr][nvs][nt], noise [ns][nvs][nt]
     (standard normal, unscaled), onset [nr][nvs] and the event parameters."""
     g = streams(wl.seed)
-    xs, xr, xv = positions(wl.ns, wl), positions(wl.nr, wl), positions(wl.nvs, wl)
+    xs, xr, xv = positions(wl.ns, wl), positions(wl.nr, wl), vs_positions(wl)
     dev, rev = down_events(wl, g[0]), reflection_events(wl, g[1])
     out = {
         "d": event_cube(xs, xr, wl.nt, wl.dt, wl.f0, dev),

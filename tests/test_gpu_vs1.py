@@ -1,0 +1,192 @@
+"""A single virtual source (nvs = 1): the per-frequency products are matrix-vector
+products (cost analysis, Appendix A), run by their own one-pass kernel with the batch
+rows of a frequency split into row groups.  Every kind (forward, adjoint, fused
+gradient), the steps, the full gradient and the two single-virtual-source workloads
+against the FP64 oracle; every precision setting runs these products in float32."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import freq, optim
+
+from gpu_helpers import H, T, batch, f32, make_plan, random_case, relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+# (nr, nb): one receiver; pairs per thread 1, 2, 4 and 8 (nr up to 4096); one row group
+# (nb <= 8) and several, with ragged last groups.
+CASES = [(1, 1), (37, 8), (37, 30), (201, 64), (530, 17), (1100, 40), (4000, 64)]
+
+
+@pytest.mark.parametrize("nr,nb", CASES, ids=[f"nr{a}-nb{b}" for a, b in CASES])
+def test_operators(nr, nb):
+    ns, nt, nf = 70, 128, 65
+    d, u, r = random_case(ns, nr, 1, nt, seed=nr + nb)
+    plan = make_plan(d, u, nb_max=nb, nf=nf)
+    idx = batch(ns, nb, seed=nb)
+    it = T(idx, torch.int32)
+    ug = plan.mdc_forward(T(r), it)
+    assert relerr(H(ug), freq.mdc(d[idx], r, nf)) <= TOL
+    gg = plan.mdc_adjoint(T(u[idx]), it)
+    assert relerr(H(gg), freq.mdc_adjoint(d[idx], u[idx], nf)) <= TOL
+    G, loss, gn = plan.mdd_stoch_grad(T(r), it)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= TOL
+    assert abs(loss.item() - lo) <= TOL * lo
+    g2 = float(np.sum(go * go))
+    assert abs(gn.item() - g2) <= 2 * TOL * g2
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "bf16"])
+def test_every_precision_setting_is_float32(prec):
+    ns, nr, nt, nf, nb = 50, 150, 256, 100, 24
+    d, u, r = random_case(ns, nr, 1, nt, seed=5)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, precision=prec)
+    ref = make_plan(d, u, nb_max=nb, nf=nf)
+    idx = T(batch(ns, nb, seed=2), torch.int32)
+    G, loss, gn = plan.mdd_stoch_grad(T(r), idx)
+    G0, loss0, gn0 = ref.mdd_stoch_grad(T(r), idx)
+    assert torch.equal(G, G0) and torch.equal(loss, loss0) and torch.equal(gn, gn0)
+    lo, go = freq.batch_loss_grad(d, r, u, H(idx).astype(int), nf)
+    assert relerr(H(G), go) <= TOL
+
+
+@pytest.mark.parametrize("nb", [4, 20])
+def test_bad_and_repeated_indices(nb):
+    """Indices outside [0, ns) act as sources with zero wavefields; a repeated index
+    counts twice (the sum over the batch)."""
+    ns, nr, nt, nf = 30, 45, 256, 120
+    d, u, r = random_case(ns, nr, 1, nt, seed=nb)
+    plan = make_plan(d, u, nb_max=nb, nf=nf)
+    good = batch(ns, nb - 3, seed=1)
+    idx = np.concatenate([good[:1], [ns + 2], good, [-1]])[:nb]
+    idx[2] = idx[0]
+    kept = [int(i) for i in idx if 0 <= i < ns]
+    G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx.astype(np.int32), torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, kept, nf)
+    assert relerr(H(G), go) <= TOL
+    assert abs(loss.item() - lo) <= TOL * lo
+    ug = plan.mdc_forward(T(r), T(idx.astype(np.int32), torch.int32))
+    want = np.zeros((nb, 1, nt))
+    ok = (idx >= 0) & (idx < ns)
+    want[ok] = freq.mdc(d[idx[ok]], r, nf)
+    assert relerr(H(ug), want) <= TOL
+
+
+def test_deterministic_bitwise():
+    ns, nr, nt, nf, nb = 64, 300, 256, 100, 64
+    d, u, r = random_case(ns, nr, 1, nt, seed=9)
+    plan = make_plan(d, u, nb_max=nb, nf=nf)
+    idx = T(batch(ns, nb, seed=3), torch.int32)
+    g1, l1, n1 = [x.clone() for x in plan.mdd_stoch_grad(T(r), idx)]
+    for _ in range(3):
+        g2, l2, n2 = plan.mdd_stoch_grad(T(r), idx)
+        assert torch.equal(g1, g2) and torch.equal(l1, l2) and torch.equal(n1, n2)
+
+
+@pytest.mark.parametrize("opt", ["sgd", "adam", "nsgd"])
+@pytest.mark.parametrize("store_rf", [False, True])
+def test_steps_match_oracle(opt, store_rf):
+    wl = synth.WORKLOADS["line2d_vs1"]
+    ns, nr, nt, nf, nb = 41, 35, 256, 100, 16
+    d, u, r0 = random_case(ns, nr, 1, nt, seed=17)
+    onset = synth.onsets(wl.replace(dt=0.002, vs_first=17), nr, 1)
+    plan = make_plan(d, u, onset=onset, nb_max=nb, nf=nf, store_rf=store_rf)
+    R = T(r0)
+    s0 = torch.zeros_like(R)
+    s1 = torch.zeros_like(R)
+    ro = r0.copy()
+    m = np.zeros_like(ro)
+    v = np.zeros_like(ro)
+    lr = {"sgd": 2e-4, "adam": 1e-2, "nsgd": 1e-4}[opt]
+    perm = synth.epoch_permutations(wl, 1, ns=ns)[0]
+    for t, b in enumerate(optim.batches(perm, nb), start=1):
+        loss, _ = plan.mdd_step(R, T(b, torch.int32), opt=opt, lr=lr, s0=s0, s1=s1, t=t, mu=0.9)
+
+        def grad(x, b=b):
+            return optim.apply_mask(freq.batch_loss_grad(d, x, u, b, nf)[1], onset)
+        lo = freq.batch_loss_grad(d, ro + (0.9 * m if opt == "nsgd" else 0.0), u, b, nf)[0]
+        assert abs(loss.item() - lo) <= TOL * lo
+        if opt == "sgd":
+            ro = optim.sgd(ro, grad(ro), lr, onset)
+        elif opt == "adam":
+            ro, m, v = optim.adam(ro, m, v, grad(ro), t, lr, onset=onset)
+        else:
+            ro, m = optim.nesterov(ro, m, grad, lr, 0.9, onset)
+    assert relerr(H(R) - r0, ro - r0) <= 1e-4
+    if opt != "sgd":
+        assert relerr(H(s0), m) <= 1e-4
+
+
+@pytest.mark.parametrize("nb_max", [8, 24, 64])
+def test_full_gradient_and_landweber(nb_max):
+    """Full gradient (the row-group partials summed into the second spectra buffer over
+    the batches) and two Landweber iterations with stored spectra."""
+    from oracle import stepsize
+    from paper_2202_04486_amd.plan import Plan
+    ns, nr, nt, nf = 70, 60, 256, 90
+    d, u, r0 = random_case(ns, nr, 1, nt, seed=nb_max)
+    plan = Plan(ns, nr, 1, nt, nf, nb_max, store_rf=True, full_grad=True)
+    plan.mdd_set_kernel(T(d))
+    plan.mdd_set_data(T(u))
+    G, loss, gn = plan.mdd_full_grad(T(r0))
+    lo, go = freq.batch_loss_grad(d, r0, u, np.arange(ns), nf)
+    assert relerr(H(G), go) <= TOL
+    assert abs(loss.item() - lo) <= TOL * lo
+    s2, _ = stepsize.sigma_max2_kernel(d, nf)
+    lr = 1.0 / s2
+    R = T(r0)
+    ro = r0.copy()
+    for _ in range(2):
+        loss, _ = plan.mdd_full_step(R, opt="sgd", lr=lr)
+        lo, go = freq.batch_loss_grad(d, ro, u, np.arange(ns), nf)
+        assert abs(loss.item() - lo) <= TOL * lo
+        ro = optim.sgd(ro, go, lr)
+    assert relerr(H(R) - r0, ro - r0) <= 1e-4
+
+
+def test_line2d_single_virtual_source_gradient():
+    """The 2D line with one virtual source at receiver 100 (201 sources and receivers,
+    1024 samples, 257 bins, batches of 32, mask), from the closed-form events."""
+    wl = synth.WORKLOADS["line2d_vs1"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    r = f32(synth.random_arrays(3, (wl.nr, 1, wl.nt))[0])
+    u = f32(synth.random_arrays(4, (wl.ns, 1, wl.nt))[0])
+    plan = make_plan(d, u, onset=p["onset"], nb_max=wl.nb, nf=wl.nf)
+    for seed in range(3):
+        idx = batch(wl.ns, wl.nb, seed=seed)
+        G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+        lo, go = freq.batch_loss_grad(d, r, u, idx, wl.nf)
+        assert relerr(H(G), optim.apply_mask(go, p["onset"])) <= TOL
+        assert abs(loss.item() - lo) <= TOL * lo
+
+
+def test_patch3d_single_virtual_source_gradient():
+    """The 3D patch with one virtual source at grid point (20, 20): 1600 sources and
+    receivers, 512 samples, 200 bins, batches of 64 in four row groups per frequency.
+    D from the closed-form events, generated on the device; the oracle takes the
+    batch's rows of the same float32 cube."""
+    wl = synth.WORKLOADS["patch3d_vs1"]
+    dev = torch.device("cuda", 0)
+    xs, xr = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl)
+    dd = synth.cube_on_device(xs, xr, wl, synth.down_events(wl), dev)
+    r = f32(synth.random_arrays(5, (wl.nr, 1, wl.nt))[0])
+    u = f32(synth.random_arrays(6, (wl.ns, 1, wl.nt))[0])
+    from paper_2202_04486_amd.plan import Plan
+    plan = Plan(wl.ns, wl.nr, 1, wl.nt, wl.nf, wl.nb)
+    plan.mdd_set_kernel(dd)
+    plan.mdd_set_data(T(u))
+    idx = batch(wl.ns, wl.nb, seed=7)
+    G, loss, gn = plan.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    d_rows = H(dd[torch.as_tensor(idx, device=dev).long()])
+    del dd
+    lo, go = freq.batch_loss_grad(d_rows, r, u[idx], np.arange(wl.nb), wl.nf)
+    assert relerr(H(G), go) <= TOL
+    assert abs(loss.item() - lo) <= TOL * lo
+    g2 = float(np.sum(go * go))
+    assert abs(gn.item() - g2) <= 2 * TOL * g2

@@ -309,6 +309,23 @@ def test_mask_passes_true_response():
     assert leak < 1e-6 * np.abs(r).max()
 
 
+@pytest.mark.parametrize("name", ["line2d_vs1", "patch3d_vs1"])
+def test_single_virtual_source_workloads(name):
+    """The one virtual source sits at the middle receiver position, its column of the
+    multi-source workload: same onsets, same true response, and the mask passes it."""
+    wl = synth.WORKLOADS[name]
+    full = synth.WORKLOADS[name.replace("_vs1", "")]
+    assert wl.nvs == 1 and synth.vs_positions(full).shape[0] == full.nvs
+    np.testing.assert_array_equal(synth.vs_positions(wl)[0], synth.positions(full.nr, full)[wl.vs_first])
+    np.testing.assert_array_equal(synth.onsets(wl)[:, 0], synth.onsets(full)[:, wl.vs_first])
+    p = synth.make_problem(wl.replace(ns=4, nt=256), with_noise=False)
+    xr = synth.positions(full.nr, full)
+    col = synth.event_cube(xr, xr[[wl.vs_first]], 256, wl.dt, wl.f0, p["r_events"])
+    np.testing.assert_array_equal(p["r_true"], col)
+    leak = np.abs(p["r_true"] - optim.apply_mask(p["r_true"], p["onset"])).max()
+    assert leak < 1e-6 * np.abs(p["r_true"]).max()
+
+
 def test_reciprocity_self_adjoint_idempotent():
     z, w = rand((5, 5, 8), 35), rand((5, 5, 8), 36)
     cz = optim.reciprocity(z)
