@@ -19,7 +19,9 @@ iteration (every source, SGD) is timed beside the stochastic epoch.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
                     [--workload line2d|patch3d|line2d_vs1|patch3d_vs1]
 
-Prints one JSON line.  Inputs are resident in HBM before timing starts.
+Prints one JSON line.  Inputs are resident in HBM before timing starts.  `value` is
+timed over K steps with no instrumentation; the per-kernel durations behind the
+roofline come from HIP events on the plan's stream over K further steps.
 """
 from __future__ import annotations
 
@@ -150,7 +152,7 @@ def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2
         lr = 0.5 * 2.0 / float(plan.mdd_sigma_max2(iters=100).max().item())
     R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
     m, v = torch.zeros_like(R), torch.zeros_like(R)
-    loss = torch.zeros(warmup + steps, dtype=torch.float64, device=dev)
+    loss = torch.zeros(warmup + 2 * steps, dtype=torch.float64, device=dev)
     gn = torch.zeros_like(loss)
 
     def step(j):
@@ -160,13 +162,19 @@ def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2
     for j in range(warmup):
         step(j)
     torch.cuda.synchronize()
-    plan.profile_enable(True, capacity=8 * steps + 64)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for j in range(warmup, warmup + steps):
         step(j)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # Per-kernel durations: HIP events around every launch, over the next `steps` steps.
+    # They are taken apart from the throughput above because each event record on the
+    # stream adds a few microseconds between kernels.
+    plan.profile_enable(True, capacity=8 * steps + 64)
+    torch.cuda.synchronize()
+    for j in range(warmup + steps, warmup + 2 * steps):
+        step(j)
+    torch.cuda.synchronize()
     prof = plan.profile_read()
     plan.profile_enable(False)
     losses = loss.cpu().numpy()
@@ -279,7 +287,7 @@ def main():
     u = up_going(p0, r_true, noise, wl, dev)
     del p0, r_true, noise
     torch.cuda.empty_cache()
-    idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + args.steps, dev)
+    idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + 2 * args.steps, dev)
     torch.cuda.synchronize()
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -382,6 +390,9 @@ def main():
         "epoch_ms": ms_step * spe,
         "steps_per_epoch": spe,
         "kernel_ms": cls_ms,
+        "kernel_ms_source": "HIP events on the plan's stream around every launch, over K steps "
+                            "run right after the K timed ones (the event records add a few us "
+                            "between kernels, so value is timed without them)",
         "dominant_kernel": dominant,
         "workload": args.workload,
         "roofline": roofline,
