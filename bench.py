@@ -152,7 +152,7 @@ def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2
         lr = 0.5 * 2.0 / float(plan.mdd_sigma_max2(iters=100).max().item())
     R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
     m, v = torch.zeros_like(R), torch.zeros_like(R)
-    loss = torch.zeros(warmup + 2 * steps, dtype=torch.float64, device=dev)
+    loss = torch.zeros(warmup + 3 * steps, dtype=torch.float64, device=dev)
     gn = torch.zeros_like(loss)
 
     def step(j):
@@ -177,8 +177,17 @@ def run_form(form, wl, d, u, onset_t, idx_tab, lens, warmup, steps, dev, lr=1e-2
     torch.cuda.synchronize()
     prof = plan.profile_read()
     plan.profile_enable(False)
+    # Distribution of single-step times: one event pair per step over K more steps.
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i, j in enumerate(range(warmup + 2 * steps, warmup + 3 * steps)):
+        step(j)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     losses = loss.cpu().numpy()
-    return plan, R, elapsed, prof, losses
+    return plan, R, elapsed, prof, losses, per_step
 
 
 def source_hash(path):
@@ -238,7 +247,32 @@ def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
         r, m, v = optim.adam(r, m, v, optim.apply_mask(g, onset), n + 1, 1e-2, onset=onset)
         n += 1
     el = time.perf_counter() - t0
+    one = None
+    try:  # the same sample on one core (BLAS and FFT threads limited to 1)
+        from threadpoolctl import threadpool_limits
+        r = np.zeros((wl.nr, wl.nvs, wl.nt))
+        m = np.zeros_like(r)
+        v = np.zeros_like(r)
+        with threadpool_limits(1):
+            n1 = 0
+            t1 = time.perf_counter()
+            while n1 < len(bs) and (time.perf_counter() - t1) < budget_s:
+                _, g = freq.batch_loss_grad(d64, r, u64, bs[n1], wl.nf)
+                r, m, v = optim.adam(r, m, v, optim.apply_mask(g, onset), n1 + 1, 1e-2, onset=onset)
+                n1 += 1
+            one = n1 / (time.perf_counter() - t1)
+    except ImportError:
+        pass
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n / el, "unit": "grad evals/s", "cores": int(cores), "kind": "oracle",
+            "one_core_value": one, "cpu_model": model,
             "sample": f"{n} Adam steps (batches of {wl.nb}) of the first epoch of the 201-trace "
                       f"line, oracle.freq gradient + oracle.optim.adam in float64, {el:.1f} s"}, errs
 
@@ -287,7 +321,7 @@ def main():
     u = up_going(p0, r_true, noise, wl, dev)
     del p0, r_true, noise
     torch.cuda.empty_cache()
-    idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + 2 * args.steps, dev)
+    idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + 3 * args.steps, dev)
     torch.cuda.synchronize()
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -308,7 +342,7 @@ def main():
     R_eval = None
     for form in forms:
         log(f"timing {form}")
-        plan, R, el, prof, losses = run_form(form, wl, d, u, onset_t, idx_tab, lens,
+        plan, R, el, prof, losses, per_step = run_form(form, wl, d, u, onset_t, idx_tab, lens,
                                              args.warmup, args.steps, dev,
                                              store_rf=not args.no_store_rf)
         if R_eval is None:
@@ -316,7 +350,7 @@ def main():
         g, _, _ = plan.mdd_stoch_grad(R_eval, idx0)
         grads[form] = g.clone()
         res[form] = {"elapsed": el, "prof": prof, "loss_first": float(losses[0]),
-                     "loss_last": float(losses[-1])}
+                     "loss_last": float(losses[-1]), "per_step": per_step}
         del plan
         torch.cuda.synchronize()
 
@@ -398,6 +432,9 @@ def main():
         "roofline": roofline,
         "method_roofline_frac": (alg_bytes / HBM_PEAK_GBS / 1e9) / (ms_step * 1e-3),
         "gemm_roofline": {f: gemm_roof(f) for f in forms},
+        "step_ms_quantiles": {q: float(np.percentile(fp["per_step"], v))
+                              for q, v in (("p10", 10), ("median", 50), ("p90", 90))},
+        "step_ms_quantiles_source": "one HIP event pair per step over K further steps",
         "forms": {f: {"value": K / res[f]["elapsed"], "ms_per_step": 1e3 * res[f]["elapsed"] / K,
                       "speedup_vs_fp32": fp["elapsed"] / res[f]["elapsed"],
                       "gemm_speedup_vs_fp32": per_launch(fp["prof"], "gemm") /

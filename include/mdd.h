@@ -159,6 +159,13 @@ mdd_status mdc_adjoint(mdd_plan* plan, const float* V, const int32_t* idx, int32
 mdd_status mdd_stoch_grad(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
                           float* G_out, double* loss_out, double* gnorm2_out);
 
+/* Host-side check of a batch before it is enqueued: idx_host [nb] in host memory.
+ * The device entry points treat an index outside [0, ns) as a source with zero
+ * wavefields; callers that want such an index to be an error check the batch here.
+ * Returns EINVAL (NULL, or an index outside [0, ns)) or ESHAPE (nb outside
+ * [1, nb_max]).  Calls no HIP function. */
+mdd_status mdd_check_batch_host(const int32_t* idx_host, int32_t nb, int32_t ns, int32_t nb_max);
+
 /* One stochastic step in place: the gradient of mdd_stoch_grad at R (or, for
  * MDD_OPT_NSGD, at R + mu s0), then the update of R and of the optimiser state
  * s0, s1 ([nr][nvs][nt] float32 each): SGD uses neither (may be NULL), NSGD

@@ -536,6 +536,14 @@ mdd_status mdd_reciprocity(const float* z, float* out, int32_t n, int32_t nt, vo
              : MDD_EHIP;
 }
 
+mdd_status mdd_check_batch_host(const int32_t* idx_host, int32_t nb, int32_t ns, int32_t nb_max) {
+  if (!idx_host) return MDD_EINVAL;
+  if (nb < 1 || nb > nb_max) return MDD_ESHAPE;
+  for (int32_t b = 0; b < nb; ++b)
+    if (idx_host[b] < 0 || idx_host[b] >= ns) return MDD_EINVAL;
+  return MDD_OK;
+}
+
 mdd_status mdd_invalidate_model_spectra(mdd_plan* p) {
   if (!p) return MDD_EINVAL;
   p->spec_model = nullptr;

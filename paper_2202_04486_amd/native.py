@@ -22,7 +22,8 @@ KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft")
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
            "mdd_set_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward", "mdc_adjoint",
            "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
-           "mdd_reciprocity", "mdd_invalidate_model_spectra", "mdd_sigma_max2",
+           "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
+           "mdd_sigma_max2",
            "mdd_profile_enable", "mdd_profile_read", "mdd_status_string",
            "mdd_plan_last_hip_error")
 
@@ -75,6 +76,7 @@ def load() -> ctypes.CDLL:
         "mdd_full_grad": (_I32, [_P, _P, _P, _P, _P]),
         "mdd_full_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _P]),
         "mdd_reciprocity": (_I32, [_P, _P, _I32, _I32, _P]),
+        "mdd_check_batch_host": (_I32, [_P, _I32, _I32, _I32]),
         "mdd_invalidate_model_spectra": (_I32, [_P]),
         "mdd_sigma_max2": (_I32, [_P, _I32, _P]),
         "mdd_profile_enable": (_I32, [_P, _I32, _I32]),

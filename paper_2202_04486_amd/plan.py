@@ -189,6 +189,14 @@ class Plan:
                    _ptr(loss_out), _ptr(gnorm2_out))
         return loss_out, gnorm2_out
 
+    def mdd_check_batch_host(self, idx):
+        """Raise MddError if the batch has the wrong size or an index outside [0, ns)
+        (the device entry points treat such an index as a zero source).  Host only."""
+        host = (idx.detach().cpu() if isinstance(idx, torch.Tensor) else torch.as_tensor(idx))
+        host = host.to(torch.int32).contiguous()
+        check("mdd_check_batch_host", self.lib.mdd_check_batch_host(
+            ctypes.c_void_p(host.data_ptr()), host.numel(), self.ns, self.nb_max))
+
     def mdd_invalidate_model_spectra(self):
         self._call("mdd_invalidate_model_spectra")
 

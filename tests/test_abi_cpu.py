@@ -119,3 +119,25 @@ def test_plan_refuses_cpu_device():
     from paper_2202_04486_amd.plan import Plan
     with pytest.raises(ValueError):
         Plan(8, 8, 8, 128, 65, 4, device="cpu")
+
+
+def test_check_batch_host(lib):
+    """The host-side batch check: sizes against nb_max, indices against [0, ns)."""
+    def check(idx, ns=10, nb_max=4):
+        arr = (ctypes.c_int32 * max(1, len(idx)))(*idx)
+        return lib.mdd_check_batch_host(arr, len(idx), ns, nb_max)
+    assert check([0, 3, 9]) == native.MDD_OK
+    assert check([2, 2]) == native.MDD_OK                    # repeats are allowed
+    assert check([0, 10]) == native.MDD_EINVAL
+    assert check([-1]) == native.MDD_EINVAL
+    assert check([]) == native.MDD_ESHAPE
+    assert check([0, 1, 2, 3, 4]) == native.MDD_ESHAPE
+    assert lib.mdd_check_batch_host(None, 1, 10, 4) == native.MDD_EINVAL
+
+
+def test_reciprocity_rejects_bad_arguments_on_the_host(lib):
+    p = ctypes.c_void_p(4096)
+    assert lib.mdd_reciprocity(None, p, 4, 128, None) == native.MDD_EINVAL
+    assert lib.mdd_reciprocity(ctypes.c_void_p(4100), p, 4, 128, None) == native.MDD_EINVAL
+    assert lib.mdd_reciprocity(p, p, 0, 128, None) == native.MDD_ESHAPE
+    assert lib.mdd_reciprocity(p, p, 4, 100, None) == native.MDD_ESHAPE

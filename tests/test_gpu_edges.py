@@ -153,3 +153,16 @@ def test_large_batch_small_operators(prec, tol, nr, nvs):
     lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
     assert relerr(H(G), go) <= tol
     assert abs(loss.item() - lo) <= tol * lo
+
+
+def test_check_batch_host_through_the_binding():
+    """Plan.mdd_check_batch_host accepts a valid device batch and rejects an index
+    outside [0, ns) or an oversize batch, which the device path would take as a
+    zero source or refuse."""
+    from paper_2202_04486_amd import MddError
+    d, u, r = random_case(12, 8, 8, 128, seed=3)
+    plan = make_plan(d, u, nb_max=4, nf=65)
+    plan.mdd_check_batch_host(T(np.array([0, 11, 11]), torch.int32))
+    for bad in ([0, 12], [-1], [0, 1, 2, 3, 4]):
+        with pytest.raises(MddError):
+            plan.mdd_check_batch_host(T(np.array(bad), torch.int32))
