@@ -63,7 +63,10 @@ typedef int32_t mdd_status;
 #define MDD_EUNSUPPORTED (-5) /* precision or optimiser not available */
 #define MDD_ESTATE (-6)       /* kernel / data not set before a call that needs them */
 
-/* Arithmetic of the two per-frequency complex products. */
+/* Arithmetic of the two per-frequency complex products.  With one virtual source
+ * (nvs = 1) the products are matrix-vector products bound by the bytes of D_b and
+ * run in float32 on the vector units whatever the setting (Appendix A: the
+ * matrix-matrix product reduces to a matrix-vector product there). */
 #define MDD_PREC_FP32 0   /* float32 MFMA, float32 accumulate */
 #define MDD_PREC_BF16X3 1 /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, float32 accumulate */
 #define MDD_PREC_FP16X3 2 /* fp16 hi+lo split with power-of-two tile scaling, float32 accumulate */

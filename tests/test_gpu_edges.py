@@ -166,3 +166,49 @@ def test_check_batch_host_through_the_binding():
     for bad in ([0, 12], [-1], [0, 1, 2, 3, 4]):
         with pytest.raises(MddError):
             plan.mdd_check_batch_host(T(np.array(bad), torch.int32))
+
+
+def test_steps_replay_from_a_captured_hip_graph():
+    """mdd_step enqueues only kernels on the caller's stream, so torch's graph capture
+    records it.  Three captured Adam steps, replayed three times from the same
+    starting state with eager library work between the replays, give the eager
+    result bitwise every time."""
+    ns, nr, nvs, nt, nf, nb = 30, 20, 17, 256, 100, 8
+    d, u, r0 = random_case(ns, nr, nvs, nt, seed=51)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, store_rf=True)
+    R = T(r0)
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    idx = [T(batch(ns, nb, seed=s), torch.int32) for s in range(3)]
+    loss = torch.zeros(3, dtype=torch.float64, device=R.device)
+
+    def steps():
+        for j in range(3):
+            plan.mdd_step(R, idx[j], opt="adam", lr=1e-2, s0=m, s1=v, t=j + 1,
+                          loss_out=loss[j:j + 1])
+
+    def reset():
+        R.copy_(T(r0))
+        m.zero_()
+        v.zero_()
+        loss.zero_()
+        plan.mdd_invalidate_model_spectra()
+
+    reset()
+    steps()
+    torch.cuda.synchronize()
+    want = (R.clone(), m.clone(), v.clone(), loss.clone())
+    reset()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        steps()
+    for rep in range(3):
+        reset()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (R, m, v, loss)
+        assert all(torch.equal(a, b) for a, b in zip(got, want)), rep
+        plan.mdd_invalidate_model_spectra()
+        plan.mdd_stoch_grad(T(r0), idx[rep])          # eager work between replays
+        torch.cuda.synchronize()
