@@ -5,10 +5,10 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 Layouts (C order, time fastest): d [ns][nr][nt] down-going wavefield,
 R [nr][nvs][nt] local reflection response, u [ns][nvs][nt] up-going wavefield.
 
-Conventions (the paper is silent on them; see the reading list in the design doc):
+Conventions (readings taken where the paper is silent on them):
 forward DFT X[k] = sum_t x[t] exp(-2 pi i k t / nt) with no normalisation,
 inverse with 1/nt; nfft = nt, so products of spectra are circular convolutions;
-bins k < nf are retained and the kernel d is band-limited to them (O1 below),
+bins k < nf are retained and the kernel d is band-limited to them (`bandlimit`),
 unit quadrature weights in the receiver integral.
 """
 from __future__ import annotations
@@ -42,7 +42,7 @@ def retained_bins(nt: int, nf: int) -> np.ndarray:
 
 
 def bandlimit(x: np.ndarray, nf: int) -> np.ndarray:
-    """Project real traces onto the first nf one-sided frequency bins (O1).
+    """Project real traces onto the first nf one-sided frequency bins.
 
     The frequency-domain form of the operator (the per-frequency matrix product of
     the Theory section, evaluated only for the retained bins) is exactly the time-
