@@ -216,6 +216,44 @@ def stored_traffic(workload, key):
         return None
 
 
+def error_per_epoch(wl, d, u, onset_t, onset, forms, epochs, dev):
+    """Each form's gradient error against the FP64 oracle at the end of each epoch of
+    its own Adam run (untimed): the gradient on the next epoch's first batch at the
+    form's current model, against the oracle's gradient at that same model."""
+    import torch
+
+    import synth
+    from oracle import freq, optim
+    from paper_2202_04486_amd.plan import Plan
+    from paper_2202_04486_amd.solver import batches
+    d64 = d.double().cpu().numpy()
+    u64 = u.double().cpu().numpy()
+    perms = synth.epoch_permutations(wl, epochs + 1)
+    out = {}
+    for form in forms:
+        plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, precision=form, store_rf=True,
+                    device=dev)
+        plan.mdd_set_kernel(d)
+        plan.mdd_set_data(u)
+        plan.mdd_set_mask(onset_t)
+        R = torch.zeros((wl.nr, wl.nvs, wl.nt), dtype=torch.float32, device=dev)
+        m, v = torch.zeros_like(R), torch.zeros_like(R)
+        t, errs = 0, []
+        for e in range(epochs):
+            for b in batches(perms[e], wl.nb):
+                t += 1
+                plan.mdd_step(R, torch.as_tensor(b, dtype=torch.int32, device=dev), opt="adam",
+                              lr=1e-2, s0=m, s1=v, t=t)
+            b0 = np.sort(perms[e + 1][:wl.nb])
+            g, _, _ = plan.mdd_stoch_grad(R, torch.as_tensor(b0, dtype=torch.int32, device=dev))
+            _, go = freq.batch_loss_grad(d64, R.double().cpu().numpy(), u64, b0, wl.nf)
+            go = optim.apply_mask(go, onset)
+            errs.append(float(np.linalg.norm(g.double().cpu().numpy() - go) / np.linalg.norm(go)))
+        out[form] = errs
+        del plan
+    return out
+
+
 def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
     """The FP64 oracle, as it stands, timed on the host cores on a bounded sample
     of the same workload (Adam steps on the first batches), and the gradient
@@ -291,6 +329,9 @@ def main():
     ap.add_argument("--no-full-gradient", action="store_true",
                     help="skip timing the full-gradient iteration (every source per update)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--error-epochs", type=int, default=5,
+                    help="epochs of each form's untimed run whose ends are checked against the "
+                         "oracle (with the CPU-baseline leg)")
     ap.add_argument("--no-store-rf", action="store_true",
                     help="recompute the model spectra at each step instead of storing them")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -453,6 +494,10 @@ def main():
         out["cpu_baseline"] = cb
         for f in forms:
             out["forms"][f]["grad_rel_err_vs_fp64_oracle"] = errs[f]
+        log("gradient error per epoch against the oracle")
+        per_epoch = error_per_epoch(wl, d, u, onset_t, onset, forms, args.error_epochs, dev)
+        for f in forms:
+            out["forms"][f]["grad_rel_err_per_epoch"] = per_epoch[f]
     print(json.dumps(out), flush=True)
 
 

@@ -96,3 +96,24 @@ def test_line2d_adam_smooth_eps_full_size(line2d):
     diff, ro = _adam_run(line2d, 16.0, lr=lr)
     assert np.linalg.norm(diff) <= 1e-4 * np.linalg.norm(ro)
     assert diff.max() <= 1e-2 * lr
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16x3", 1e-3)])
+def test_line2d_error_per_epoch(line2d, prec, tol):
+    """The precision form over its own Adam run: at the end of each of two epochs the
+    gradient on the next epoch's first batch, at the form's current model, against the
+    oracle's gradient at that same model."""
+    wl, d, u, onset = line2d
+    plan = make_plan(d, u, onset=onset, nb_max=wl.nb, nf=wl.nf, precision=prec, store_rf=True)
+    R = torch.zeros(wl.nr, wl.nvs, wl.nt, device="cuda")
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    perms = synth.epoch_permutations(wl, 3)
+    t = 0
+    for e in range(2):
+        for b in optim.batches(perms[e], wl.nb):
+            t += 1
+            plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=1e-2, s0=m, s1=v, t=t)
+        b0 = optim.batches(perms[e + 1], wl.nb)[0]
+        g, _, _ = plan.mdd_stoch_grad(R, T(b0, torch.int32))
+        _, go = freq.batch_loss_grad(d, H(R), u, b0, wl.nf)
+        assert relerr(H(g), optim.apply_mask(go, onset)) <= tol, e
