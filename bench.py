@@ -13,11 +13,13 @@ against the FP64 oracle.  `--workload patch3d` runs the 1600-trace 3D patch
 (40 x 40 grid at 25 m, 512 samples, 200 bins, batches of 64) instead;
 `line2d_vs1` and `patch3d_vs1` invert for one virtual source in the middle of
 the line (batches of 32, Nesterov momentum) or of the patch (batches of 64,
-Adam), where the products are matrix-vector products.  One full-gradient
+Adam), where the products are matrix-vector products; `diff301` times the
+differentiation form (a gradient through torch.autograd at 301 traces for
+batches of 8, 32 and 64, and the reciprocity kernel).  One full-gradient
 iteration (every source, SGD) is timed beside the stochastic epoch.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-                    [--workload line2d|patch3d|line2d_vs1|patch3d_vs1]
+                    [--workload line2d|patch3d|line2d_vs1|patch3d_vs1|diff301]
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.  `value` is
 timed over K steps with no instrumentation; the per-kernel durations behind the
@@ -52,6 +54,9 @@ WORKLOAD_TEXT = {
                    "noise-free, stored model spectra",
 }
 DEFAULT_EPOCHS = {"line2d": 10, "patch3d": 1, "line2d_vs1": 50, "patch3d_vs1": 10}
+AUTOGRAD_TEXT = ("diff301: differentiation form, ns=nr=nvs=301 (10 m line), nt=1024, nf=257, "
+                 "loss 1/2 ||mdc(C_r z) - u_b||^2 through torch.autograd (mdc_forward / "
+                 "mdc_adjoint and the reciprocity kernel), random N(0,1) model, batches 8 / 32 / 64")
 # Model-sized float32 arrays each update reads and writes (R and the optimiser state).
 STATE_ARRAYS = {"adam": 3, "nsgd": 2, "sgd": 1}
 HBM_PEAK_GBS = 8000.0
@@ -315,13 +320,98 @@ def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
                       f"line, oracle.freq gradient + oracle.optim.adam in float64, {el:.1f} s"}, errs
 
 
+def bench_autograd(args, dev):
+    """Differentiation form: one gradient of 1/2 ||mdc(C_r z) - u_b||^2 with respect to
+    z through torch.autograd, whose backward runs the adjoint kernel and the reciprocity
+    kernel again.  Timed per batch size; kernel times from the plan's HIP events over
+    separate evaluations; the reciprocity kernel timed on its own."""
+    import torch
+
+    import synth
+    from paper_2202_04486_amd.autograd import _reciprocity, mdc, reciprocity
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["diff301"]
+    log("generating inputs")
+    d, r_true, noise, _ = make_inputs(wl, dev)
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, max(wl.nb_sweep), device=dev)
+    plan.mdd_set_kernel(d)
+    u = up_going(plan, r_true, noise, wl, dev)
+    del r_true, noise
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wl.seed)
+    z = torch.randn((wl.nr, wl.nvs, wl.nt), generator=gen, device=dev).requires_grad_(True)
+    K = args.steps or 20
+    W = args.warmup if args.warmup is not None else 3
+    by_batch = {}
+    for nb in wl.nb_sweep:
+        idx_tab, lens, _ = step_tables(wl, nb, W + 2 * K, dev)
+
+        def ev(j):
+            idx = idx_tab[j, :lens[j]]
+            pred = mdc(reciprocity(z), idx, plan)
+            loss = 0.5 * ((pred - u.index_select(0, idx.long())) ** 2).sum()
+            return torch.autograd.grad(loss, z)[0]
+
+        for j in range(W):
+            ev(j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(W, W + K):
+            ev(j)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        plan.profile_enable(True, capacity=16 * K + 64)
+        for j in range(W + K, W + 2 * K):
+            ev(j)
+        torch.cuda.synchronize()
+        prof = plan.profile_read()
+        plan.profile_enable(False)
+        gemm_ms = prof["gemm"][0] / K          # forward and adjoint product launches per evaluation
+        flops = 16.0 * nb * wl.nr * wl.nvs * wl.nf
+        by_batch[nb] = {"value": K / el, "ms_per_eval": 1e3 * el / K,
+                        "kernel_ms_per_eval": {k: v[0] / K for k, v in prof.items() if v[1]},
+                        "products_tflops": flops / (gemm_ms * 1e-3) / 1e12,
+                        "products_mfma_frac": flops / (gemm_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+    # the reciprocity kernel alone: z read once, the result written once
+    zz = z.detach()
+    for _ in range(3):
+        _reciprocity(zz)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        _reciprocity(zz)
+    e1.record()
+    torch.cuda.synchronize()
+    rec_ms = e0.elapsed_time(e1) / 20
+    rec_bytes = 8.0 * wl.nr * wl.nvs * wl.nt
+    top = by_batch[max(wl.nb_sweep)]
+    out = {
+        "metric": METRIC, "value": top["value"], "unit": "grad evals/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": top["ms_per_eval"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": AUTOGRAD_TEXT, "global_batch": max(wl.nb_sweep), "seq_len": wl.nt,
+                   "parallelism": "none (1 GPU)"},
+        "workload": "diff301",
+        "roofline": {"kernel": "products (forward and adjoint launches) at the largest batch",
+                     "bound": "mfma", "achieved": top["products_tflops"],
+                     "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": top["products_mfma_frac"], "traffic": None,
+                     "algorithmic_flops": 16.0 * max(wl.nb_sweep) * wl.nr * wl.nvs * wl.nf},
+        "reciprocity": {"ms": rec_ms, "algorithmic_bytes": rec_bytes,
+                        "achieved_gbs": rec_bytes / (rec_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "frac": rec_bytes / (rec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "by_batch": by_batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 10 epochs of line2d, 1 epoch of patch3d)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="line2d", choices=list(WORKLOAD_TEXT),
+    ap.add_argument("--workload", default="line2d", choices=list(WORKLOAD_TEXT) + ["diff301"],
                     help="line2d (default, the headline), the 1600-trace 3D patch, or either "
                          "with a single virtual source")
     ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
@@ -344,6 +434,9 @@ def main():
     import torch
 
     import synth
+    if args.workload == "diff301":
+        bench_autograd(args, torch.device("cuda", 0))
+        return
     wl = synth.WORKLOADS[args.workload]
     spe0 = math.ceil(wl.ns / wl.nb)
     if args.steps is None:
