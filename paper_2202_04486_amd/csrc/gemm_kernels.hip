@@ -14,8 +14,9 @@
 //       stays in LDS between the two products.  Every kind and precision.
 //   k_gemm_pipe   fp32, fused, nb <= 16, nr <= PIPE_KC: persistent, the next
 //       item's R_k in flight during the current item's products.
-//   k_gemm_ws     fp32, fused, 33 <= nb <= 64: loader waves stream R_k through
-//       an LDS ring for the compute waves; the adjoint needs no barrier.
+//   k_gemm_ws<kind>  fp32, 33 <= nb <= 64, every kind: loader waves stream R_k
+//       through an LDS ring for the compute waves; the adjoint needs no barrier
+//       (the adjoint kind reads the batch spectra into the residual planes).
 // R_k is read and G_k written exactly once.  G_k goes over R_k, or (the full
 // gradient) into, or added to, a second spectra buffer.
 //
@@ -529,6 +530,7 @@ constexpr int WF_DP = WF_KC + 4;              // D slot row pitch [b][r] (comple
 constexpr int WF_RP = 64 + 16;                // ring / residual row pitch [r or b][col]
 constexpr size_t WF_SMEM = sizeof(float2) * (2 * 64 * WF_DP + 2 * WF_KC * WF_RP);
 
+template <int KIND>
 __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
   constexpr int MB = 64, NW = 64, KC = WF_KC;
   constexpr int NCT = 64 * WF_CW, NLT = 64 * WF_LW;
@@ -577,7 +579,17 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
   };
   auto d_ok = [&](int b, int r) { return s_drow[b] >= 0 && r < a.nr; };
 
-  if (compute) {
+  if constexpr (KIND == GK_ADJ) {  // the residual planes are the batch spectra V_k
+    if (compute) {
+      for (int i = tid; i < MB * NW; i += NCT) {
+        const int row = i / NW, col = i % NW, blk = blk0 + col / CB;
+        float2 z = make_float2(0.f, 0.f);
+        if (row < a.nb && blk0 * CB + col < a.nvs && s_idx[row] >= 0)
+          z = a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + (col & 15)];
+        s_res[row * WF_RP + col] = z;
+      }
+    }
+  } else if (compute) {
     float4 dv[FPT];
     auto load_d = [&](int c) {
 #pragma unroll
@@ -629,6 +641,19 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
       __syncthreads();
     }
 
+    if constexpr (KIND == GK_FWD) {  // P_k = D_b R_k -> batch spectra
+#pragma unroll
+      for (int t = 0; t < TPC; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = (rt0 + t) * 16 + lq * 4 + e, col = nt_w * 16 + lr, blk = blk0 + nt_w;
+          if (row < a.nb && blk < a.nvb) {
+            const bool ok = blk0 * CB + col < a.nvs && s_idx[row] >= 0;
+            a.Bsp[(((size_t)row * a.nvb + blk) * a.nf + k) * CB + lr] =
+                ok ? make_float2(ar[t][e], ai[t][e]) : make_float2(0.f, 0.f);
+          }
+        }
+    } else {
     // residual and float64 loss partial
     float2 uv[TPC][4];
 #pragma unroll
@@ -658,6 +683,7 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
     }
     lpart = wave_sum(lpart);
     if (lane == 0) s_red[wave] = lpart;
+    }
   } else {
     float4 rq[WF_DEPTH][LPT];
     auto issue = [&](float4 (&dst)[LPT], int c) {
@@ -708,12 +734,14 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
     }
   }
   __syncthreads();  // residual complete; the last barrier of the loader waves
-  if (tid == 0) {
-    double tot = 0.0;
-    for (int w = 0; w < WF_CW; ++w) tot += s_red[w];
-    a.loss_part[logical] = tot;
+  if constexpr (KIND == GK_FUSED) {
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < WF_CW; ++w) tot += s_red[w];
+      a.loss_part[logical] = tot;
+    }
   }
-  if (!compute) return;
+  if (!compute || KIND == GK_FWD) return;
 
   // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
   const int nrt = (a.nr + 15) / 16;
@@ -923,6 +951,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+template <int KIND>
+hipError_t launch_ws(const GemmArgs& a, hipStream_t s) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_ws<KIND>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)WF_SMEM);
+  const int ncg = (a.nvb + 3) / 4;
+  hipLaunchKernelGGL(k_gemm_ws<KIND>, dim3(a.nf * ncg), dim3(WF_THREADS), WF_SMEM, s, a);
+  return hipGetLastError();
+}
+
 template <int PREC, int NBT, int TNB>
 hipError_t launch_cfg(int kind, const GemmArgs& a, hipStream_t s) {
   using C = GemmCfg<PREC, NBT, TNB>;
@@ -975,12 +1012,11 @@ hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
   } else {
     if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
     if constexpr (PREC == MDD_PREC_FP32) {
-      if (kind == GK_FUSED) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_ws),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)WF_SMEM);
-        const int ncg = (a.nvb + 3) / 4;
-        hipLaunchKernelGGL(k_gemm_ws, dim3(a.nf * ncg), dim3(WF_THREADS), WF_SMEM, s, a);
-        return hipGetLastError();
+      switch (kind) {
+        case GK_FUSED: return launch_ws<GK_FUSED>(a, s);
+        case GK_FWD: return launch_ws<GK_FWD>(a, s);
+        case GK_ADJ: return launch_ws<GK_ADJ>(a, s);
+        default: return hipErrorInvalidValue;
       }
     }
     return launch_cfg<PREC, 4, 4>(kind, a, s);

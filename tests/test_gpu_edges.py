@@ -7,7 +7,7 @@ import torch
 import synth
 from oracle import freq, optim
 
-from gpu_helpers import H, T, batch, make_plan, random_case, relerr
+from gpu_helpers import H, T, batch, f32, make_plan, random_case, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -212,3 +212,24 @@ def test_steps_replay_from_a_captured_hip_graph():
         plan.mdd_invalidate_model_spectra()
         plan.mdd_stoch_grad(T(r0), idx[rep])          # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nb", [33, 47, 64])
+def test_fp32_operators_large_batches(nb):
+    """The forward and adjoint operators alone at 33..64 batch rows in fp32 (the
+    warp-specialised kernel's forward and adjoint kinds): receivers not a multiple of the
+    64-receiver chunk, columns not a multiple of the 64-column group, a repeated index and
+    two rejected ones (zero rows of the forward output, no adjoint contribution)."""
+    ns, nr, nvs, nt, nf = 80, 131, 70, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + 71)
+    plan = make_plan(d, u, nb_max=nb, nf=nf)
+    good = batch(ns, nb - 3, seed=nb)
+    idx = np.concatenate([good, [good[0], -1, ns]]).astype(np.int32)
+    ok = (idx >= 0) & (idx < ns)
+    ug = plan.mdc_forward(T(r), T(idx, torch.int32))
+    want = np.zeros((nb, nvs, nt))
+    want[ok] = freq.mdc(d[idx[ok]], r, nf)
+    assert relerr(H(ug), want) <= 1e-5
+    v = synth.random_arrays(nb, (nb, nvs, nt))[0]
+    gg = plan.mdc_adjoint(T(v), T(idx, torch.int32))
+    assert relerr(H(gg), freq.mdc_adjoint(d[idx[ok]], f32(v)[ok], nf)) <= 1e-5
