@@ -190,3 +190,38 @@ def test_patch3d_single_virtual_source_gradient():
     assert abs(loss.item() - lo) <= TOL * lo
     g2 = float(np.sum(go * go))
     assert abs(gn.item() - g2) <= 2 * TOL * g2
+
+
+def test_line2d_vs1_nsgd_epochs_match_oracle():
+    """The single-virtual-source 2D workload in the configuration the benchmark runs:
+    Nesterov momentum 0.9 at half the kernel-derived step 2 / sigma_max^2 (Appendix B),
+    batches of 32 (7 per epoch, the last one partial), causality mask, stored model
+    spectra, over three epochs against the oracle's trajectory on the same batches."""
+    from oracle import stepsize
+    wl = synth.WORKLOADS["line2d_vs1"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    u_clean = freq.mdc(d, f32(p["r_true"]), wl.nf)
+    u = f32(u_clean + synth.scale_noise(u_clean, p["noise"], wl.snr_db))
+    onset = p["onset"]
+    s2, _ = stepsize.sigma_max2_kernel(d, wl.nf)
+    lr = 0.5 * 2.0 / s2
+    plan = make_plan(d, u, onset=onset, nb_max=wl.nb, nf=wl.nf, store_rf=True)
+    R = torch.zeros(wl.nr, 1, wl.nt, device="cuda")
+    vel = torch.zeros_like(R)
+    ro = np.zeros((wl.nr, 1, wl.nt))
+    vo = np.zeros_like(ro)
+    losses = []
+    for perm in synth.epoch_permutations(wl, 3):
+        for b in optim.batches(perm, wl.nb):
+            loss, _ = plan.mdd_step(R, T(b, torch.int32), opt="nsgd", lr=lr, s0=vel, mu=0.9)
+
+            def grad(x, b=b):
+                return optim.apply_mask(freq.batch_loss_grad(d, x, u, b, wl.nf)[1], onset)
+            lo = freq.batch_loss_grad(d, ro + 0.9 * vo, u, b, wl.nf)[0]
+            assert abs(loss.item() - lo) <= 1e-5 * lo
+            losses.append(lo)
+            ro, vo = optim.nesterov(ro, vo, grad, lr, 0.9, onset)
+        assert relerr(H(R), ro) <= 1e-4
+    assert relerr(H(vel), vo) <= 1e-4
+    assert np.mean(losses[-7:]) < np.mean(losses[:7])      # it is converging
