@@ -44,7 +44,8 @@ Layout make_layout(const mdd_dims& d) {
   // nvs = 1: the matrix-vector products write one loss partial per row group.
   const size_t ngv = d.nvs == 1 ? gemv_groups(d.nb_max, d.nf) : 0;
   L.lossp = take(sizeof(double) * d.nf * (ngv > nvb ? ngv : nvb));
-  L.gnp = take(sizeof(double) * d.nr * nvb * 2);  // gradient / update modes: up to 2 per block
+  // gradient / update modes: one partial per workgroup, trace_update_split(nt) per block
+  L.gnp = take(sizeof(double) * d.nr * nvb * trace_update_split(d.nt));
   L.dmx = take(sizeof(float) * d.nf);               // per-frequency max |D| (fp16 scaling)
   L.red2 = take(sizeof(double) * 512);              // two-level reduction stage
   const bool full = (d.flags & MDD_FLAG_FULL_GRAD) != 0;  // full gradient: G buffer, sources, losses
