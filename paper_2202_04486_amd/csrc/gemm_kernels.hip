@@ -741,9 +741,10 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
       a.loss_part[logical] = tot;
     }
   }
-  if (!compute || KIND == GK_FWD) return;
+  if (KIND == GK_FWD) return;
 
-  // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
+  // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k; the
+  // loader waves, their ring work done, take tiles too
   const int nrt = (a.nr + 15) / 16;
   auto load_tile = [&](float2 (&d)[16], int mt) {  // conj D operand: b = ks*4 + lq
     const int r = min(mt * 16 + lr, a.nr - 1);
@@ -753,11 +754,11 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
   float2 dn[16];
   load_tile(dn, min(wave, nrt - 1));
 #pragma unroll 1
-  for (int mt = wave; mt < nrt; mt += WF_CW) {
+  for (int mt = wave; mt < nrt; mt += WF_CW + WF_LW) {
     float2 dc[16];
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) dc[ks] = dn[ks];
-    load_tile(dn, min(mt + WF_CW, nrt - 1));
+    load_tile(dn, min(mt + WF_CW + WF_LW, nrt - 1));
     const int r = mt * 16 + lr;
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks)

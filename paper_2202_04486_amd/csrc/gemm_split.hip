@@ -736,6 +736,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
 // ring of float32 values.  D_{b,k} chunks are double-buffered as well, so a
 // single barrier separates consecutive chunks.  (With one role per wave, each
 // wave has one chunk in flight and waits on memory for about half of its time.)
+// In the barrier-free adjoint all twelve waves take receiver tiles.
 constexpr int WS_DEPTH = 3;
 constexpr int WS_CW = 8;                   // compute waves (two per SIMD)
 constexpr int WS_LW = 4;                   // loader waves
@@ -1049,8 +1050,9 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   }
   const float2 ss = scale_of(s_max, WS_CW);
 
-  // adjoint, without barriers: G_k = D_b^H Res_k.  Each compute wave owns the
-  // receiver tiles wave, wave + WS_CW, ...; it loads its tile's A operand (conj D:
+  // adjoint, without barriers: G_k = D_b^H Res_k.  Every wave (the loader waves too,
+  // their ring work being done) owns the receiver tiles wave, wave + WS_CW + WS_LW,
+  // ...; it loads its tile's A operand (conj D:
   // eight batch rows of one receiver per lane and k-step) from L2 straight into
   // registers, splitting it there (the next tile's values are in flight during
   // the current tile's products).  The residual planes in LDS are the B operand.
@@ -1065,8 +1067,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       }
     }
   }
-  __syncthreads();  // the last barrier: the loader waves are done
-  if (!compute) return;
+  __syncthreads();  // the last barrier: the ring is no longer used
   const int nrt = (a.nr + 15) / 16;
   auto load_tile = [&](float2 (&d)[2][8], int mt) {  // clamped: always in bounds
     const int r = min(mt * 16 + lr, a.nr - 1);
@@ -1078,13 +1079,13 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   float2 dn[2][8];
   load_tile(dn, min(wave, nrt - 1));
 #pragma unroll 1
-  for (int mt = wave; mt < nrt; mt += WS_CW) {
+  for (int mt = wave; mt < nrt; mt += WS_CW + WS_LW) {
     float2 dc[2][8];
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int e = 0; e < 8; ++e) dc[kk][e] = dn[kk][e];
-    load_tile(dn, min(mt + WS_CW, nrt - 1));
+    load_tile(dn, min(mt + WS_CW + WS_LW, nrt - 1));
     const int r = mt * 16 + lr;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
