@@ -77,6 +77,9 @@ typedef int32_t mdd_status;
                                next mdd_step on the same R skips its forward transform */
 #define MDD_FLAG_FULL_GRAD 2 /* reserve a second spectra buffer and the list of all sources
                                 for mdd_full_grad / mdd_full_step */
+#define MDD_FLAG_STREAM_KERNEL 4 /* keep no kernel spectra for all sources: the caller stages
+                                    each batch's rows with mdd_stage_kernel (the kernel may
+                                    then live out of device memory); not with FULL_GRAD */
 
 /* Sizes.  ns sources, nr receivers, nvs virtual sources, nt time samples
  * (128, 256, 512 or 1024), nf retained one-sided frequency bins (1..nt/2+1),
@@ -161,6 +164,19 @@ mdd_status mdc_adjoint(mdd_plan* plan, const float* V, const int32_t* idx, int32
  * float64 scalars (either may be NULL).  Needs kernel and data. */
 mdd_status mdd_stoch_grad(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
                           float* G_out, double* loss_out, double* gnorm2_out);
+
+/* Kernel rows of one batch, for a plan with MDD_FLAG_STREAM_KERNEL (Examples and
+ * Appendix A: with 3D acquisitions the kernel may not fit in memory; a step only
+ * uses the nb rows of its batch).  d_rows [nb][nr][nt] float32 device: row b is
+ * the down-going wavefield of the source the next call's idx[b] names.  The
+ * following mdc_forward / mdc_adjoint / mdd_stoch_grad / mdd_step on this plan
+ * must pass a batch of the same length nb, and take D row b from here (U still
+ * from idx[b]; an index outside [0, ns) still acts as a zero source).  d_rows may
+ * be reused once the stream has passed this call.  mdd_set_kernel, mdd_sigma_max2
+ * and the full gradient need every source and return ESTATE on such a plan.
+ * Errors: EINVAL (NULL), ESTATE (plan without the flag), ESHAPE (nb outside
+ * [1, nb_max]), EHIP. */
+mdd_status mdd_stage_kernel(mdd_plan* plan, const float* d_rows, int32_t nb);
 
 /* Host-side check of a batch before it is enqueued: idx_host [nb] in host memory.
  * The device entry points treat an index outside [0, ns) as a source with zero

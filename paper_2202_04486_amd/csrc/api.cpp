@@ -34,7 +34,9 @@ Layout make_layout(const mdd_dims& d) {
     return at;
   };
   L.tw = take(c8 * 2 * d.nt);  // twiddle tables (at most 2 nt entries)
-  L.df = take(c8 * d.nf * d.ns * nrp);
+  // kernel spectra: every source, or (MDD_FLAG_STREAM_KERNEL) the staged batch rows
+  const size_t drows = (d.flags & MDD_FLAG_STREAM_KERNEL) ? d.nb_max : d.ns;
+  L.df = take(c8 * d.nf * drows * nrp);
   L.uf = take(c8 * d.nf * d.ns * nvsp);
   L.oob = take(sizeof(double) * d.ns);
   L.oobp = take(sizeof(double) * d.ns * nvb);
@@ -65,7 +67,9 @@ mdd_status check_dims(const mdd_dims* d) {
   if (d->nf > d->nt / 2 + 1) return MDD_ESHAPE;
   if (d->nb_max > d->ns || d->nb_max > NB_LIMIT) return MDD_ESHAPE;
   if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_BF16) return MDD_EUNSUPPORTED;
-  if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD)) return MDD_EINVAL;
+  if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD | MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
+  // the full gradient visits every source: it needs the resident kernel spectra
+  if ((d->flags & MDD_FLAG_FULL_GRAD) && (d->flags & MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
   return MDD_OK;
 }
 
@@ -116,6 +120,17 @@ struct mdd_plan {
   double* lossb() const { return at<double>(L.lossb); }
   float4* gvp() const { return at<float4>(L.gvp); }
   bool full() const { return (d.flags & MDD_FLAG_FULL_GRAD) != 0; }
+  // MDD_FLAG_STREAM_KERNEL: Df holds the rows of the last staged batch (staged_nb rows).
+  bool streamed() const { return (d.flags & MDD_FLAG_STREAM_KERNEL) != 0; }
+  int staged_nb = 0;
+  // A call on a batch of nb entries: with staged kernel rows, the batch must be the
+  // staged one (same length; entry b uses staged row b).
+  mdd_status batch_ok(int nb) const {
+    if (nb < 1 || nb > d.nb_max) return MDD_ESHAPE;
+    if (streamed() && staged_nb == 0) return MDD_ESTATE;
+    if (streamed() && nb != staged_nb) return MDD_ESHAPE;
+    return MDD_OK;
+  }
   // One virtual source: the time arrays [rows][1][nt] are handled as one row of `rows`
   // columns, so spectra blocks hold 16 receivers (or batch rows), and the products are
   // matrix-vector products.
@@ -181,6 +196,8 @@ struct mdd_plan {
     g.nf = d.nf;
     g.nt = d.nt;
     g.nb = nb;
+    g.dns = streamed() ? d.nb_max : d.ns;
+    g.dpos = streamed() ? 1 : 0;
     if (vs1()) {
       g.P = gemv_groups(nb, d.nf);
       g.gpart = gvp();
@@ -349,6 +366,7 @@ mdd_status mdd_plan_set_stream(mdd_plan* plan, void* stream) {
 
 mdd_status mdd_set_kernel(mdd_plan* p, const float* d) {
   if (!p || !d) return MDD_EINVAL;
+  if (p->streamed()) return MDD_ESTATE;  // such a plan takes batch rows (mdd_stage_kernel)
   TraceArgs a{};
   a.nt = p->d.nt;
   a.nf = p->d.nf;
@@ -364,8 +382,36 @@ mdd_status mdd_set_kernel(mdd_plan* p, const float* d) {
   MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
   if (p->d.precision == MDD_PREC_FP16X3)
     MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] {
-      return launch_freq_absmax(p->Df(), p->d.nf, (long long)p->d.ns * p->nrp, p->dmx(), p->stream);
+      return launch_freq_absmax(p->Df(), p->d.nf, (long long)p->d.ns * p->nrp,
+                                (long long)p->d.ns * p->nrp, p->dmx(), p->stream);
     }));
+  p->kernel_set = true;
+  return MDD_OK;
+}
+
+mdd_status mdd_stage_kernel(mdd_plan* p, const float* d_rows, int32_t nb) {
+  if (!p || !d_rows) return MDD_EINVAL;
+  if (!p->streamed()) return MDD_ESTATE;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  TraceArgs a{};
+  a.nt = p->d.nt;
+  a.nf = p->d.nf;
+  a.rows = nb;
+  a.ncols = p->d.nr;
+  a.ncb = nblocks(p->d.nr);
+  a.x_in = d_rows;
+  a.spec = p->Df();
+  a.s_row = p->nrp;
+  a.s_cb = CB;
+  a.s_k = (long long)p->d.nb_max * p->nrp;
+  a.tw = p->tw();
+  MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  if (p->d.precision == MDD_PREC_FP16X3)
+    MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] {
+      return launch_freq_absmax(p->Df(), p->d.nf, (long long)nb * p->nrp,
+                                (long long)p->d.nb_max * p->nrp, p->dmx(), p->stream);
+    }));
+  p->staged_nb = nb;
   p->kernel_set = true;
   return MDD_OK;
 }
@@ -408,7 +454,7 @@ mdd_status mdd_set_mask(mdd_plan* p, const int32_t* onset) {
 
 mdd_status mdc_forward(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb, float* U_out) {
   if (!p || !R || !idx || !U_out) return MDD_EINVAL;
-  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set) return MDD_ESTATE;
   p->spec_model = nullptr;
   MDD_TRY(p->model_fft(R, nullptr, 0.0));
@@ -421,7 +467,7 @@ mdd_status mdc_forward(mdd_plan* p, const float* R, const int32_t* idx, int32_t 
 
 mdd_status mdc_adjoint(mdd_plan* p, const float* V, const int32_t* idx, int32_t nb, float* G_out) {
   if (!p || !V || !idx || !G_out) return MDD_EINVAL;
-  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set) return MDD_ESTATE;
   p->spec_model = nullptr;
   TraceArgs a = p->blocked(p->Bsp(), nb);
@@ -437,7 +483,7 @@ mdd_status mdc_adjoint(mdd_plan* p, const float* V, const int32_t* idx, int32_t 
 mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb,
                           float* G_out, double* loss_out, double* gnorm2_out) {
   if (!p || !R || !idx || !G_out) return MDD_EINVAL;
-  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
   p->spec_model = nullptr;
   MDD_TRY(p->model_fft(R, nullptr, 0.0));
@@ -454,7 +500,7 @@ mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32
 mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* opt,
                     const int32_t* idx, int32_t nb, double* loss_out, double* gnorm2_out) {
   if (!p || !R || !opt || !idx) return MDD_EINVAL;
-  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
   TraceArgs a = p->blocked(p->F(), p->d.nr);
   int mode = 0;
@@ -554,7 +600,7 @@ mdd_status mdd_invalidate_model_spectra(mdd_plan* p) {
 mdd_status mdd_sigma_max2(mdd_plan* p, int32_t iters, double* lam_out) {
   if (!p || !lam_out) return MDD_EINVAL;
   if (iters < 1) return MDD_EINVAL;
-  if (!p->kernel_set) return MDD_ESTATE;
+  if (!p->kernel_set || p->streamed()) return MDD_ESTATE;  // needs every source's D_k
   return p->run(MDD_KC_REDUCE, [&] {
     return launch_sigma(p->Df(), p->d.nf, p->d.ns, p->d.nr, p->nrp, iters, lam_out, p->stream);
   });

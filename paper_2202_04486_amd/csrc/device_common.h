@@ -39,6 +39,13 @@ __device__ __forceinline__ void store_g(const GemmArgsT& a, long long off, float
   *p = v;
 }
 
+// Row of D_k for batch entry b whose source s is valid: s in the resident spectra,
+// b in spectra staged for the batch.
+template <class GemmArgsT>
+__device__ __forceinline__ int drow_of(const GemmArgsT& a, int b, int s) {
+  return a.dpos ? b : s;
+}
+
 __device__ __forceinline__ double block_sum256(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         if (s < 0 || s >= a.ns) s = -1;
       }
       s_idx[b] = s;
-      s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+      s_drow[b] = s >= 0 ? ((long long)k * a.dns + drow_of(a, b, s)) * a.nrp : -1;
     }
     __syncthreads();
   };
@@ -568,11 +568,11 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
       if (s < 0 || s >= a.ns) s = -1;
     }
     s_idx[b] = s;
-    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+    s_drow[b] = s >= 0 ? ((long long)k * a.dns + drow_of(a, b, s)) * a.nrp : -1;
   }
   __syncthreads();
 
-  const long long drow0 = (long long)k * a.ns * a.nrp;
+  const long long drow0 = (long long)k * a.dns * a.nrp;
   auto d_at = [&](int b, int r) -> long long {  // always in bounds
     const long long off = s_drow[b];
     return (off >= 0 ? off : drow0) + (r < a.nr ? r : 0);
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (s < 0 || s >= a.ns) s = -1;
     }
     s_idx[tid] = s;
-    s_drow[tid] = s >= 0 ? (long long)s * a.nrp : -1;   // row offset within one frequency
+    s_drow[tid] = s >= 0 ? (long long)drow_of(a, tid, s) * a.nrp : -1;  // within one frequency
   }
   __syncthreads();
 
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const long long off = s_drow[b];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (off >= 0 && rr < a.nr)
-        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.ns * a.nrp + off + rr);
+        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.dns * a.nrp + off + rr);
       s_d[b * DST + rr] = make_float2(v.x, v.y);
       s_d[b * DST + rr + 1] = make_float2(v.z, v.w);
     }

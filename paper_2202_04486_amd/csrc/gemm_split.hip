@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
       if (s < 0 || s >= a.ns) s = -1;
     }
     s_idx[b] = s;
-    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+    s_drow[b] = s >= 0 ? ((long long)k * a.dns + drow_of(a, b, s)) * a.nrp : -1;
   }
   __syncthreads();
 
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
       if (s < 0 || s >= a.ns) s = -1;
     }
     s_idx[tid] = s;
-    s_drow[tid] = s >= 0 ? (long long)s * a.nrp : -1;  // row offset within one frequency
+    s_drow[tid] = s >= 0 ? (long long)drow_of(a, tid, s) * a.nrp : -1;  // within one frequency
   }
   __syncthreads();
 
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
       const long long off = s_drow[b];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (off >= 0 && rr < a.nr) {
-        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.ns * a.nrp + off + rr);
+        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.dns * a.nrp + off + rr);
         if (rr + 1 >= a.nr) v.z = v.w = 0.f;
       }
       dv[q] = v;
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       if (s < 0 || s >= a.ns) s = -1;
     }
     s_idx[b] = s;
-    s_drow[b] = s >= 0 ? ((long long)k * a.ns + s) * a.nrp : -1;
+    s_drow[b] = s >= 0 ? ((long long)k * a.dns + drow_of(a, b, s)) * a.nrp : -1;
   }
   __syncthreads();
 
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   // ---- compute side: D chunks for the forward product ([b][r] planes)
   // D loads are unconditional too (a rejected index reads row 0 of the frequency,
   // a receiver beyond nr reads receiver 0); staging zeroes them.
-  const long long drow0 = (long long)k * a.ns * a.nrp;
+  const long long drow0 = (long long)k * a.dns * a.nrp;
   auto d_at = [&](int b, int r) -> long long {
     const long long off = s_drow[b];
     return (off >= 0 ? off : drow0) + (r < a.nr ? r : 0);

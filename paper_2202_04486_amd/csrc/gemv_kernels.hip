@@ -110,7 +110,7 @@ __global__ __launch_bounds__(GV_THREADS) void k_gemv(GemmArgs a) {
       int s = ii < i1 ? a.idx[ii] : -1;
       if (s < 0 || s >= a.ns) s = -1;
       src[r] = s;
-      const long long row = ((long long)k * a.ns + (s < 0 ? 0 : s)) * (a.nrp / 2);
+      const long long row = ((long long)k * a.dns + (s < 0 ? 0 : drow_of(a, ii, s))) * (a.nrp / 2);
 #pragma unroll
       for (int m = 0; m < MQ; ++m) {
         const int q = tid + GV_THREADS * m;

@@ -82,6 +82,9 @@ struct GemmArgs {
   float2* Gout;           // adjoint product destination (same layout as F); NULL: over R_k in F
   int gacc;               // 1: add the adjoint product to Gout instead of writing it
   int ns, nr, nrp, nvs, nvsp, nvb, nf, nt, nb;
+  // Rows of D per frequency in Df (ns, or nb_max for staged batch rows) and where batch
+  // entry b finds its row: 0 = row idx[b] (resident spectra), 1 = row b (staged).
+  int dns, dpos;
   // Single virtual source (launch_gemv): row groups per frequency and their adjoint
   // partials [nf][P][nrp / 2] (receiver pairs).
   int P;
@@ -108,8 +111,8 @@ hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, 
                           hipStream_t s);
 hipError_t launch_iota(int32_t* out, int n, hipStream_t s);
 hipError_t launch_reciprocity(const float* z, float* out, int n, int nt, hipStream_t s);
-hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out,
-                              hipStream_t s);
+hipError_t launch_freq_absmax(const float2* Df, int nf, long long count, long long stride,
+                              float* out, hipStream_t s);
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,
                         double* lam_out, hipStream_t s);
 

@@ -138,8 +138,12 @@ __global__ __launch_bounds__(256) void k_sigma(const float2* Df, int ns, int nr,
 // Largest |Re| or |Im| of D_k over all sources and receivers, per frequency (the
 // fp16 split forms scale D_{b,k} by a power of two derived from it).  One
 // workgroup per frequency; a maximum does not depend on the order.
-__global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long per_freq, float* out) {
-  const float2* x = Df + (long long)blockIdx.x * per_freq;
+// Largest |Re|, |Im| of the first `count` entries of each frequency's block (blocks
+// `stride` entries apart).
+__global__ __launch_bounds__(256) void k_freq_absmax(const float2* Df, long long count,
+                                                     long long stride, float* out) {
+  const float2* x = Df + (long long)blockIdx.x * stride;
+  const long long per_freq = count;
   float m = 0.f;
   for (long long i = threadIdx.x; i < per_freq; i += 256) m = fmaxf(m, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
 #pragma unroll
@@ -201,8 +205,9 @@ hipError_t launch_iota(int32_t* out, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_freq_absmax(const float2* Df, int nf, long long per_freq, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_freq_absmax, dim3(nf), dim3(256), 0, s, Df, per_freq, out);
+hipError_t launch_freq_absmax(const float2* Df, int nf, long long count, long long stride,
+                              float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_freq_absmax, dim3(nf), dim3(256), 0, s, Df, count, stride, out);
   return hipGetLastError();
 }
 

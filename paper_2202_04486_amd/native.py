@@ -15,12 +15,14 @@ MDD_OK, MDD_EINVAL, MDD_ESHAPE, MDD_ENOMEM, MDD_EHIP, MDD_EUNSUPPORTED, MDD_ESTA
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3}
 FLAG_STORE_RF = 1
 FLAG_FULL_GRAD = 2
+FLAG_STREAM_KERNEL = 4
 OPT = {"sgd": 0, "adam": 1, "nsgd": 2}
 KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft")
 
 # Entry points the header declares (checked by the test-suite against the .so).
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
-           "mdd_set_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward", "mdc_adjoint",
+           "mdd_set_kernel", "mdd_stage_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward",
+           "mdc_adjoint",
            "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
            "mdd_sigma_max2",
@@ -67,6 +69,7 @@ def load() -> ctypes.CDLL:
         "mdd_plan_destroy": (_I32, [_P]),
         "mdd_plan_set_stream": (_I32, [_P, _P]),
         "mdd_set_kernel": (_I32, [_P, _P]),
+        "mdd_stage_kernel": (_I32, [_P, _P, _I32]),
         "mdd_set_data": (_I32, [_P, _P]),
         "mdd_set_mask": (_I32, [_P, _P]),
         "mdc_forward": (_I32, [_P, _P, _P, _I32, _P]),

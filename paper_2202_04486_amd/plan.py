@@ -41,7 +41,7 @@ class Plan:
     'fp32', 'bf16x3', 'fp16x3', 'bf16'."""
 
     def __init__(self, ns, nr, nvs, nt, nf, nb_max, precision="fp32", store_rf=False,
-                 device=None, full_grad=False):
+                 device=None, full_grad=False, stream_kernel=False):
         self.lib = load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
@@ -50,7 +50,9 @@ class Plan:
         self.precision = precision
         self.dims = make_dims(ns, nr, nvs, nt, nf, nb_max, precision,
                               (native.FLAG_STORE_RF if store_rf else 0) |
-                              (native.FLAG_FULL_GRAD if full_grad else 0))
+                              (native.FLAG_FULL_GRAD if full_grad else 0) |
+                              (native.FLAG_STREAM_KERNEL if stream_kernel else 0))
+        self.stream_kernel = stream_kernel
         nbytes = workspace_bytes(self.dims)
         if nbytes == 0:
             raise MddError("mdd_workspace_bytes", native.MDD_ESHAPE)
@@ -95,6 +97,14 @@ class Plan:
     def mdd_set_kernel(self, d):
         _need(d, "d", (self.ns, self.nr, self.nt), torch.float32, self.device)
         self._call("mdd_set_kernel", _ptr(d))
+
+    def mdd_stage_kernel(self, d_rows):
+        """Kernel rows of the next batch (stream_kernel=True): d_rows [nb][nr][nt], row b
+        the source that the next call's idx[b] names."""
+        _need(d_rows, "d_rows", None, torch.float32, self.device)
+        if d_rows.dim() != 3 or d_rows.shape[1:] != (self.nr, self.nt) or not d_rows.is_contiguous():
+            raise ValueError(f"d_rows must be contiguous [nb][{self.nr}][{self.nt}]")
+        self._call("mdd_stage_kernel", _ptr(d_rows), int(d_rows.shape[0]))
 
     def mdd_set_data(self, u):
         _need(u, "u", (self.ns, self.nvs, self.nt), torch.float32, self.device)

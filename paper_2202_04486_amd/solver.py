@@ -12,6 +12,11 @@ kernel (Appendix B): alpha = kappa * 2 / sigma_max^2, kappa = 0.4..0.6.
 FullGradientMDD is the full-gradient baseline (every source per iteration, e.g. the
 Landweber iteration) on the same kernels.
 
+StreamedKernel keeps the kernel d in pinned host memory for plans made with
+stream_kernel=True (a kernel larger than the device memory, Examples: 3D): each
+batch's rows are copied to the device on a side stream one batch ahead and
+staged on the plan (mdd_stage_kernel) just before the step that uses them.
+
 Checkpoint / resume: `state_dict` captures the model, optimiser state, step
 counter, epoch / batch cursor and the permutation in use, so an interrupted
 epoch resumes on exactly the same batches.
@@ -196,3 +201,60 @@ class FullGradientMDD:
             check_divergence(out, self.loss0, self.blowup)
         self.history.extend(out.tolist())
         return out
+
+
+class StreamedKernel:
+    """The kernel d [ns][nr][nt] float32 in pinned host memory, streamed a batch at a
+    time to a plan made with stream_kernel=True.
+
+    prefetch(idx) starts copying the rows idx[b] into one of two device buffers on a
+    side stream (default priority); stage(nb) makes the caller's current stream wait for
+    that copy and stages the rows on the plan, so the next mdd_step / mdd_stoch_grad on
+    this batch reads them.  A buffer is refilled only after the stream that staged it
+    has passed the staging (an event), so the copy of batch j + 1 overlaps step j."""
+
+    def __init__(self, plan: Plan, d_host: torch.Tensor):
+        if not plan.stream_kernel:
+            raise ValueError("StreamedKernel needs a plan made with stream_kernel=True")
+        shape = (plan.ns, plan.nr, plan.nt)
+        if tuple(d_host.shape) != shape or d_host.dtype != torch.float32 or d_host.is_cuda:
+            raise ValueError(f"d_host must be a float32 host tensor of shape {shape}")
+        if not d_host.is_pinned():
+            pinned = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+            pinned.copy_(d_host)
+            d_host = pinned
+        self.plan = plan
+        self.d = d_host.contiguous()
+        dev = plan.device
+        self.buf = [torch.empty((plan.nb_max, plan.nr, plan.nt), dtype=torch.float32, device=dev)
+                    for _ in range(2)]
+        self.copy_stream = torch.cuda.Stream(dev)
+        self.ready = [torch.cuda.Event() for _ in range(2)]
+        self.free = [torch.cuda.Event() for _ in range(2)]
+        self.nb = [0, 0]
+        self.fill = 0      # buffer the next prefetch writes
+        self.use = 0       # buffer the next stage reads
+
+    def prefetch(self, idx) -> None:
+        idx = np.asarray(idx, dtype=np.int64).ravel()
+        if not 1 <= idx.size <= self.plan.nb_max:
+            raise ValueError(f"a batch has 1..{self.plan.nb_max} entries")
+        slot = self.fill
+        s = self.copy_stream
+        s.wait_event(self.free[slot])
+        with torch.cuda.stream(s):
+            for b, src in enumerate(idx):
+                if 0 <= src < self.plan.ns:   # other entries are zero sources: row unused
+                    self.buf[slot][b].copy_(self.d[src], non_blocking=True)
+            self.ready[slot].record(s)
+        self.nb[slot] = int(idx.size)
+        self.fill ^= 1
+
+    def stage(self) -> None:
+        slot = self.use
+        cur = torch.cuda.current_stream(self.plan.device)
+        cur.wait_event(self.ready[slot])
+        self.plan.mdd_stage_kernel(self.buf[slot][:self.nb[slot]])
+        self.free[slot].record(cur)
+        self.use ^= 1
+

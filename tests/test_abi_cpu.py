@@ -61,9 +61,18 @@ def test_full_gradient_flag_reserves_a_second_spectra_buffer(lib):
     assert b - a >= spectra and (b - a) % 256 == 0
 
 
+def test_streamed_kernel_flag_keeps_only_the_batch_rows(lib):
+    """MDD_FLAG_STREAM_KERNEL: the kernel spectra shrink from ns to nb_max rows."""
+    a = native.workspace_bytes(dims(ns=200, nb_max=8))
+    b = native.workspace_bytes(dims(ns=200, nb_max=8, flags=native.FLAG_STREAM_KERNEL))
+    nrp = 32                                 # 24 receivers padded to 16
+    assert a - b >= (200 - 8) * nrp * 65 * 8 - 256
+    assert b > 0
+
+
 @pytest.mark.parametrize("kw", [dict(nf=66), dict(nt=100), dict(nt=2048), dict(nb_max=33),
                                 dict(ns=100, nb_max=65), dict(ns=0), dict(nr=-1), dict(nf=0),
-                                dict(precision=7), dict(flags=4), dict(nvs=5000)])
+                                dict(precision=7), dict(flags=8), dict(flags=6), dict(nvs=5000)])
 def test_invalid_dims_rejected(lib, kw):
     assert native.workspace_bytes(dims(**kw)) == 0
     out = ctypes.c_void_p()
@@ -94,6 +103,7 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.mdd_plan_destroy(None) == E
     assert lib.mdd_plan_set_stream(None, None) == E
     assert lib.mdd_set_kernel(None, p) == E
+    assert lib.mdd_stage_kernel(None, p, 1) == E
     assert lib.mdd_set_data(None, p) == E
     assert lib.mdd_set_mask(None, p) == E
     assert lib.mdc_forward(None, p, p, 1, p) == E

@@ -1,0 +1,137 @@
+"""Kernel rows staged per batch (MDD_FLAG_STREAM_KERNEL, for a kernel that does not fit
+in device memory): every product kernel takes D row b of the staged batch instead of row
+idx[b] of the resident spectra.  The staged rows go through the same transform as the
+resident ones, so every result equals the resident plan's bitwise (fp16x3 takes its
+scale from the staged rows only, so it is compared with the oracle), and the streaming
+helper that copies rows from pinned host memory one batch ahead gives the same
+trajectory as the resident plan."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import freq, optim
+
+from gpu_helpers import H, T, batch, make_plan, random_case, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def streamed_plan(d, u, nb_max, nf, precision="fp32", store_rf=False, onset=None):
+    from paper_2202_04486_amd.plan import Plan
+    ns, nr, nt = d.shape
+    plan = Plan(ns, nr, u.shape[1], nt, nf, nb_max, precision=precision, store_rf=store_rf,
+                stream_kernel=True)
+    plan.mdd_set_data(T(u))
+    if onset is not None:
+        plan.mdd_set_mask(T(onset, torch.int32))
+    return plan
+
+
+# (nvs, nb, precision): the persistent fp32 and split kernels (nb <= 16), the tiled ones
+# (17..32), the warp-specialised ones (33..64), and the matrix-vector kernel (nvs = 1).
+CASES = [(20, 9, "fp32"), (20, 16, "bf16x3"), (37, 30, "fp32"), (37, 30, "bf16x3"),
+         (40, 64, "fp32"), (40, 50, "bf16x3"), (1, 40, "fp32"), (1, 8, "fp32")]
+
+
+@pytest.mark.parametrize("nvs,nb,prec", CASES, ids=[f"nvs{a}-nb{b}-{c}" for a, b, c in CASES])
+def test_staged_equals_resident(nvs, nb, prec):
+    ns, nr, nt, nf = 70, 53, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + nvs)
+    res = make_plan(d, u, nb_max=nb, nf=nf, precision=prec)
+    st = streamed_plan(d, u, nb, nf, precision=prec)
+    idx = batch(ns, nb, seed=nb)
+    idx[nb // 2] = idx[0]                                    # a repeated source
+    it = T(idx, torch.int32)
+    st.mdd_stage_kernel(T(d[idx]))
+    for name, args in (("mdd_stoch_grad", (T(r), it)), ("mdc_forward", (T(r), it)),
+                       ("mdc_adjoint", (T(u[idx]), it))):
+        a = getattr(res, name)(*args)
+        b = getattr(st, name)(*args)
+        for x, y in zip(a if isinstance(a, tuple) else (a,), b if isinstance(b, tuple) else (b,)):
+            assert torch.equal(x, y), name
+    G, loss, _ = st.mdd_stoch_grad(T(r), it)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    tol = 1e-5 if prec == "fp32" else 1e-3
+    assert relerr(H(G), go) <= tol
+    assert abs(loss.item() - lo) <= tol * lo
+
+
+def test_staged_fp16x3_against_oracle():
+    ns, nr, nvs, nt, nf, nb = 60, 45, 33, 256, 100, 40
+    d, u, r = random_case(ns, nr, nvs, nt, seed=5)
+    st = streamed_plan(d, u, nb, nf, precision="fp16x3")
+    idx = batch(ns, nb, seed=1)
+    st.mdd_stage_kernel(T(d[idx]))
+    G, loss, _ = st.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= 1e-3
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+
+
+def test_bad_index_with_staged_rows():
+    """An index outside [0, ns) is a zero source whatever its staged row holds."""
+    ns, nr, nvs, nt, nf, nb = 30, 21, 18, 128, 65, 6
+    d, u, r = random_case(ns, nr, nvs, nt, seed=7)
+    st = streamed_plan(d, u, nb, nf)
+    idx = np.array([3, ns + 1, 7, -1, 12, 3], dtype=np.int32)
+    rows = np.stack([d[i] if 0 <= i < ns else np.full(d.shape[1:], 1e3) for i in idx])
+    st.mdd_stage_kernel(T(rows))
+    G, loss, _ = st.mdd_stoch_grad(T(r), T(idx, torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, [3, 7, 12, 3], nf)
+    assert relerr(H(G), go) <= 1e-5
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+
+
+def test_staged_plan_state_errors():
+    from paper_2202_04486_amd import MddError
+    ns, nr, nvs, nt, nf, nb = 20, 16, 16, 128, 65, 8
+    d, u, r = random_case(ns, nr, nvs, nt, seed=9)
+    st = streamed_plan(d, u, nb, nf)
+    idx = T(batch(ns, nb, seed=2), torch.int32)
+    with pytest.raises(MddError):                 # nothing staged yet
+        st.mdd_stoch_grad(T(r), idx)
+    with pytest.raises(MddError):                 # the kernel is not resident on this plan
+        st.mdd_set_kernel(T(d))
+    with pytest.raises(MddError):
+        st.mdd_sigma_max2(iters=5)
+    st.mdd_stage_kernel(T(d[:5]))
+    with pytest.raises(MddError):                 # the batch is not the staged length
+        st.mdd_stoch_grad(T(r), idx)
+    with pytest.raises(MddError):                 # more rows than nb_max
+        st.mdd_stage_kernel(T(np.concatenate([d[:5], d[:5]])))
+
+
+@pytest.mark.parametrize("opt,store_rf", [("adam", True), ("nsgd", False)])
+def test_streamed_epoch_from_pinned_host_memory(opt, store_rf):
+    """One epoch and a half of steps with the rows copied from pinned host memory one batch
+    ahead on a side stream: bitwise the resident plan's trajectory."""
+    from paper_2202_04486_amd.solver import StreamedKernel
+    wl = synth.WORKLOADS["tiny2d"]
+    ns, nr, nvs, nt, nf, nb = 45, 40, 33, 256, 100, 16
+    d, u, _ = random_case(ns, nr, nvs, nt, seed=13)
+    onset = synth.onsets(wl.replace(dt=0.002), nr, nvs)
+    res = make_plan(d, u, onset=onset, nb_max=nb, nf=nf, store_rf=store_rf)
+    st = streamed_plan(d, u, nb, nf, store_rf=store_rf, onset=onset)
+    ks = StreamedKernel(st, torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)))
+    perms = synth.epoch_permutations(wl, 2, ns=ns)
+    bs = optim.batches(perms[0], nb) + optim.batches(perms[1], nb)[:2]
+    lr = 1e-2 if opt == "adam" else 1e-4
+    states = []
+    for plan, streamed in ((res, False), (st, True)):
+        R = torch.zeros(nr, nvs, nt, device="cuda")
+        m, v = torch.zeros_like(R), torch.zeros_like(R)
+        losses = torch.zeros(len(bs), dtype=torch.float64, device="cuda")
+        if streamed:
+            ks.prefetch(bs[0])
+        for j, b in enumerate(bs):
+            if streamed:
+                ks.stage()
+                if j + 1 < len(bs):
+                    ks.prefetch(bs[j + 1])
+            plan.mdd_step(R, T(b, torch.int32), opt=opt, lr=lr, s0=m, s1=v, t=j + 1, mu=0.9,
+                          loss_out=losses[j:j + 1])
+        torch.cuda.synchronize()
+        states.append((R, m, v, losses))
+    for x, y in zip(*states):
+        assert torch.equal(x, y)
