@@ -136,6 +136,41 @@ def test_patch3d_gradient_sampled_columns(patch3d, prec, tol):
     torch.cuda.empty_cache()
 
 
+def test_patch3d_adam_epoch_sampled_columns(patch3d):
+    """One whole epoch (25 steps of 64 sources) of fp32 Adam with the mask and stored
+    spectra on the full 1600-trace patch, against the oracle's trajectory of 8 sampled
+    virtual-source columns (without reciprocity the columns do not interact, so the
+    oracle follows them exactly on the same batches).  eps is 1 % of the oracle's first
+    gradient rms, so the update is Lipschitz in g and every entry must follow."""
+    from paper_2202_04486_amd.plan import Plan
+    wl, d, r, u, onset, idx, cols, go0 = patch3d
+    dev = d.device
+    eps = 1e-2 * float(np.sqrt(np.mean(go0 ** 2)))
+    lr = 1e-2
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, store_rf=True)
+    plan.mdd_set_kernel(d)
+    plan.mdd_set_data(u)
+    plan.mdd_set_mask(T(onset, torch.int32))
+    R = torch.zeros(wl.nr, wl.nvs, wl.nt, device=dev)
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    oc = onset[:, cols]
+    ro = np.zeros((wl.nr, len(cols), wl.nt))
+    mo, vo = np.zeros_like(ro), np.zeros_like(ro)
+    ct = torch.from_numpy(cols).to(dev)
+    for t, b in enumerate(optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb), start=1):
+        plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=lr, s0=m, s1=v, t=t, eps=eps)
+        bt = torch.from_numpy(b.astype(np.int64)).to(dev)
+        _, g = freq.batch_loss_grad(H(d[bt]), ro, H(u[bt][:, ct, :]), np.arange(len(b)), wl.nf)
+        ro, mo, vo = optim.adam(ro, mo, vo, optim.apply_mask(g, oc), t, lr, eps=eps, onset=oc)
+    assert relerr(H(m[:, ct, :]), mo) <= 1e-5
+    assert relerr(H(v[:, ct, :]), vo) <= 1e-5
+    diff = np.abs(H(R[:, ct, :]) - ro)
+    assert np.linalg.norm(diff) <= 1e-4 * np.linalg.norm(ro)
+    assert diff.max() <= 1e-2 * lr
+    plan.close()
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n,nt", [(1, 128), (7, 256), (37, 512), (301, 1024)])
 def test_reciprocity_kernel(n, nt):
     """mdd_reciprocity: bit-exact against (z + z^T) * 0.5 in float32 (one addition and an
