@@ -179,3 +179,22 @@ def test_sigma_max_matches_svd():
     s2, per_k = stepsize.sigma_max2_kernel(d, wl.nf)
     assert abs(lam.max() - s2) <= 1e-4 * s2
     assert np.all(lam <= per_k * (1 + 1e-5) + 1e-9 * s2)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 1e-4)])
+def test_zero_gradient_at_the_true_model(prec, tol):
+    """Noise-free data u = P+ R_true (made by the oracle): every batch's loss and gradient
+    vanish at R_true, up to the arithmetic's rounding, relative to their values at 0."""
+    wl = synth.WORKLOADS["tiny2d"]
+    p = synth.make_problem(wl)
+    d = f32(p["d"])
+    r_true = f32(p["r_true"])
+    u = f32(freq.mdc(d, r_true, wl.nf))
+    plan = make_plan(d, u, nb_max=wl.nb, nf=wl.nf, precision=prec)
+    for b in optim.batches(synth.epoch_permutations(wl, 1)[0], wl.nb):
+        it = T(b, torch.int32)
+        g0, l0, _ = plan.mdd_stoch_grad(torch.zeros(wl.nr, wl.nvs, wl.nt, device="cuda"), it)
+        g0, l0 = H(g0), l0.item()
+        g1, l1, _ = plan.mdd_stoch_grad(T(r_true), it)
+        assert np.linalg.norm(H(g1)) <= tol * np.linalg.norm(g0)
+        assert l1.item() <= tol * tol * l0
