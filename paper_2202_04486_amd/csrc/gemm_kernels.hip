@@ -862,6 +862,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
   };
 
+  double lsum = 0.0;
   int cur = start;
   int k = cur / nvb, cg = cur % nvb;
   float2 bfr[KSW], bnx[KSW];
@@ -916,9 +917,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       s_res[urow * RST + ucol] = z;
     }
-    const double tot = block_sum256(lpart, s_red);   // its barriers also publish s_res
-    if (tid == 0) a.loss_part[cur] = tot;
-    __syncthreads();
+    // The loss is summed per thread over the workgroup's items (a fixed range) and
+    // reduced once at the end into the partial of its first item; the others are 0.
+    lsum += lpart;
+    if (tid == 0) a.loss_part[cur] = 0.0;
+    __syncthreads();    // publishes s_res
 
     // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
     for (int mt = wave; mt * 16 < a.nr; mt += 4) {
@@ -941,15 +944,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     if (!has_next) break;
     __syncthreads();  // every wave is done with s_d, s_part, s_res of this item
-    if (kn != k) stage_d(kn);   // new frequency (rare within one workgroup's range)
+    if (kn != k) {   // new frequency (rare within one workgroup's range)
+      stage_d(kn);
+      __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < KSW; ++q) bfr[q] = bnx[q];
     up = upn;
     cur = nxt;
     k = kn;
     cg = cgn;
-    __syncthreads();
   }
+  const double tot = block_sum256(lsum, s_red);
+  if (tid == 0) a.loss_part[start] = tot;
 }
 
 template <int KIND>
