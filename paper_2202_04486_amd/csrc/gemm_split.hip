@@ -585,6 +585,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
     return sd;
   };
 
+  double lsum = 0.0;
   int cur = start;
   int k = cur / nvb, cg = cur % nvb;
   float2 bfr[KSW][8], bnx[KSW][8];
@@ -663,16 +664,21 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
         z = make_float2(0.f, 0.f);
       }
     }
-    lpart = wave_sum(lpart);
-    const float zm = wave_max(fmaxf(fabsf(z.x), fabsf(z.y)));
-    if (lane == 0) {
-      s_red[wave] = lpart;
-      s_mx[wave] = zm;
-    }
-    __syncthreads();
-    if (tid == 0) a.loss_part[cur] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
     float2 ss = make_float2(1.f, 1.f);
-    if constexpr (T::F16) ss = pow2_scale_pair(fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
+    if constexpr (T::F16) {  // the residual's block scale needs every wave's maximum
+      lpart = wave_sum(lpart);
+      const float zm = wave_max(fmaxf(fabsf(z.x), fabsf(z.y)));
+      if (lane == 0) {
+        s_red[wave] = lpart;
+        s_mx[wave] = zm;
+      }
+      __syncthreads();
+      if (tid == 0) a.loss_part[cur] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+      ss = pow2_scale_pair(fmaxf(fmaxf(s_mx[0], s_mx[1]), fmaxf(s_mx[2], s_mx[3])));
+    } else {  // summed per thread over the workgroup's items, reduced once at the end
+      lsum += lpart;
+      if (tid == 0) a.loss_part[cur] = 0.0;
+    }
     {
       E h, l;
       T::split(z.x * ss.x, h, l);
@@ -714,7 +720,10 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
     }
     if (!has_next) break;
     __syncthreads();  // every wave is done with s_d, s_part, s_r of this item
-    if (kn != k) sd = stage_d(kn);  // new frequency (rare within one workgroup's range)
+    if (kn != k) {  // new frequency (rare within one workgroup's range)
+      sd = stage_d(kn);
+      __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < KSW; ++q)
 #pragma unroll
@@ -723,7 +732,10 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
     cur = nxt;
     k = kn;
     cg = cgn;
-    __syncthreads();
+  }
+  if constexpr (!T::F16) {
+    const double tot = block_sum256(lsum, s_red);
+    if (tid == 0) a.loss_part[start] = tot;
   }
 }
 
