@@ -61,7 +61,8 @@ AUTOGRAD_TEXT = ("diff301: differentiation form, ns=nr=nvs=301 (10 m line), nt=1
 STATE_ARRAYS = {"adam": 3, "nsgd": 2, "sgd": 1}
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
-TRAFFIC_FILE = {w: os.path.join(ROOT, "profiles", f"traffic_{w}.md") for w in WORKLOAD_TEXT}
+TRAFFIC_FILE = {w: os.path.join(ROOT, "profiles", f"traffic_{w}.md")
+                for w in list(WORKLOAD_TEXT) + ["diff301"]}
 CSRC = os.path.join(ROOT, "paper_2202_04486_amd", "csrc")
 
 
@@ -361,6 +362,18 @@ def cpu_baseline(wl, d, u, onset, R_gpu, grads, idx0, budget_s=20.0):
                       f"line, oracle.freq gradient + oracle.optim.adam in float64, {el:.1f} s"}, errs
 
 
+def copy_calibration(mib, dev):
+    """A plain device copy of `mib` MiB, whose HBM counters scale the kernels' counters."""
+    import torch
+    if not mib:
+        return
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def bench_autograd(args, dev):
     """Differentiation form: one gradient of 1/2 ||mdc(C_r z) - u_b||^2 with respect to
     z through torch.autograd, whose backward runs the adjoint kernel and the reciprocity
@@ -381,6 +394,7 @@ def bench_autograd(args, dev):
     gen = torch.Generator(device=dev)
     gen.manual_seed(wl.seed)
     z = torch.randn((wl.nr, wl.nvs, wl.nt), generator=gen, device=dev).requires_grad_(True)
+    copy_calibration(args.copy_calibration_mib, dev)
     K = args.steps or 20
     W = args.warmup if args.warmup is not None else 3
     by_batch = {}
@@ -436,9 +450,12 @@ def bench_autograd(args, dev):
         "roofline": {"kernel": "products (forward and adjoint launches) at the largest batch",
                      "bound": "mfma", "achieved": top["products_tflops"],
                      "peak": MFMA_PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-                     "frac": top["products_mfma_frac"], "traffic": None,
+                     "frac": top["products_mfma_frac"],
+                     "traffic": stored_traffic("diff301", "products"),
+                     "traffic_unit": "HBM bytes per evaluation (counters, both launches)",
                      "algorithmic_flops": 16.0 * max(wl.nb_sweep) * wl.nr * wl.nvs * wl.nf},
         "reciprocity": {"ms": rec_ms, "algorithmic_bytes": rec_bytes,
+                        "traffic": stored_traffic("diff301", "reciprocity"),
                         "achieved_gbs": rec_bytes / (rec_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                         "frac": rec_bytes / (rec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "by_batch": by_batch,
@@ -500,13 +517,7 @@ def main():
     torch.cuda.empty_cache()
     idx_tab, lens, spe = step_tables(wl, wl.nb, args.warmup + 3 * args.steps, dev)
     torch.cuda.synchronize()
-    if args.copy_calibration_mib:
-        n = args.copy_calibration_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args.copy_calibration_mib, dev)
 
     forms = [f for f in args.forms.split(",") if f]
     if "fp32" not in forms:

@@ -33,11 +33,13 @@ def test_stored_traffic_follows_the_source_hash(tmp_path, monkeypatch):
 
 
 def test_committed_summaries_match_the_current_kernels():
-    """Every counter figure bench.py reads for the 2D line, the 3D patch and the
-    single-virtual-source patch belongs to the kernel source as it is now."""
+    """Every counter figure bench.py reads for the 2D line, the 3D patch, the
+    single-virtual-source patch and the differentiation form belongs to the kernel source
+    as it is now."""
     import bench
     for workload, keys in (("line2d", ("update", "gemm_fp32")),
                            ("patch3d", ("update", "gemm_fp32", "gemm_bf16x3", "gemm_fp16x3")),
-                           ("patch3d_vs1", ("update", "gemv"))):
+                           ("patch3d_vs1", ("update", "gemv")),
+                           ("diff301", ("products", "reciprocity"))):
         for k in keys:
             assert bench.stored_traffic(workload, k) is not None, (workload, k)

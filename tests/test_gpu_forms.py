@@ -171,7 +171,8 @@ def test_patch3d_adam_epoch_sampled_columns(patch3d):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n,nt", [(1, 128), (7, 256), (37, 512), (301, 1024)])
+@pytest.mark.parametrize("n,nt", [(1, 128), (2, 1024), (7, 256), (37, 512), (300, 128),
+                                  (301, 1024)])
 def test_reciprocity_kernel(n, nt):
     """mdd_reciprocity: bit-exact against (z + z^T) * 0.5 in float32 (one addition and an
     exact halving), out of place and in place, and within rounding of the FP64 oracle."""
