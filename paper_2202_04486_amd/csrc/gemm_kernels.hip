@@ -38,6 +38,28 @@ __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Complex multiply-add C += A B on 16x16x4 tiles with three real products instead of
+// four: with A = a + ib and B = c + id (lane values of the operand fragments),
+//   t1 += a (c + d),  t2 += (a + b) d,  t3 += (b - a) c,
+// so that Re C = t1 - t2 and Im C = t1 + t3 (cmac3_finish).  The operand sums are
+// vector-unit additions on the lane values; bsum = c + d is shared by the row tiles.
+__device__ __forceinline__ void cmac3(float2 av, float2 bv, float bsum, floatx4& t1, floatx4& t2,
+                                     floatx4& t3) {
+  t1 = mfma4(av.x, bsum, t1);
+  t2 = mfma4(av.x + av.y, bv.y, t2);
+  t3 = mfma4(av.y - av.x, bv.x, t3);
+}
+
+// (t1, t2, t3) -> (Re, Im) in (t1, t2).
+__device__ __forceinline__ void cmac3_finish(floatx4& t1, floatx4& t2, const floatx4& t3) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float x = t1[e];
+    t1[e] = x - t2[e];
+    t2[e] = x + t3[e];
+  }
+}
+
 // Operand of a 16x16x32 split-precision MFMA: 8 consecutive k values of one
 // row (A) or one column (B), real and imaginary parts, hi and lo.
 template <int PREC>
@@ -279,10 +301,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       }
     }
     floatx4 acc_re[C::TPWV], acc_im[C::TPWV];
+    floatx4 acc_3[C::SPLIT ? 1 : C::TPWV];         // float32: the third product of cmac3
 #pragma unroll
     for (int t = 0; t < C::TPWV; ++t) {
       acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (!C::SPLIT) acc_3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     for (int r0 = 0; r0 < a.nr; r0 += KCMAX) {
       const int len = min(KCMAX, a.nr - r0);
@@ -317,14 +341,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         if (kk * KSTEP >= lenp) break;
         if constexpr (!C::SPLIT) {
           const float2 rv = bfr[q][0];
+          const float rsum = rv.x + rv.y;
 #pragma unroll
           for (int t = 0; t < C::TPWV; ++t) {
             const int mt = (g + t * C::G) / TNB;
-            const float2 dv = s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq];
-            acc_re[t] = mfma4(dv.x, rv.x, acc_re[t]);
-            acc_re[t] = mfma4(-dv.y, rv.y, acc_re[t]);
-            acc_im[t] = mfma4(dv.x, rv.y, acc_im[t]);
-            acc_im[t] = mfma4(dv.y, rv.x, acc_im[t]);
+            cmac3(s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq], rv, rsum, acc_re[t], acc_im[t],
+                  acc_3[t]);
           }
         } else {
           using Op = SplitOp<PREC>;
@@ -358,6 +380,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
           acc_im[t] += cim[t] * inv;
         }
       }
+    }
+
+    if constexpr (!C::SPLIT) {
+#pragma unroll
+      for (int t = 0; t < C::TPWV; ++t) cmac3_finish(acc_re[t], acc_im[t], acc_3[t]);
     }
 
     // Residual (or predicted data) and the loss partial.
@@ -462,15 +489,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       for (int nt = 0; nt < TNB; ++nt) {
         floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
         if constexpr (!C::SPLIT) {
+          floatx4 t3 = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int kk = 0; kk < MB / 4; ++kk) {
-            const float2 dv = s_d[(kk * 4 + lq) * C::DST + mt * 16 + lr];
             const float2 sv = s_res[(kk * 4 + lq) * C::RST + nt * 16 + lr];
-            re = mfma4(dv.x, sv.x, re);
-            re = mfma4(dv.y, sv.y, re);
-            im = mfma4(dv.x, sv.y, im);
-            im = mfma4(-dv.y, sv.x, im);
+            cmac3(cconj(s_d[(kk * 4 + lq) * C::DST + mt * 16 + lr]), sv, sv.x + sv.y, re, im, t3);
           }
+          cmac3_finish(re, im, t3);
         } else {
           using Op = SplitOp<PREC>;
 #pragma unroll
@@ -608,11 +633,13 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
         *reinterpret_cast<float4*>(s_d + sl * DSL + b * WF_DP + rr) = v;
       }
     };
-    floatx4 ar[TPC], ai[TPC];
+    // three real products per complex multiply-add (see cmac3): t1, t2, t3 per tile
+    floatx4 ar[TPC], ai[TPC], a3[TPC];
 #pragma unroll
     for (int t = 0; t < TPC; ++t) {
       ar[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ai[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      a3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     load_d(0);
     __syncthreads();
@@ -627,19 +654,17 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {  // rows past nr are zeros in both operands
         const float2 bv = ring[ks * 4 * WF_RP];
+        const float bsum = bv.x + bv.y;
 #pragma unroll
-        for (int t = 0; t < TPC; ++t) {
-          const float2 dv2 = dsl[t * 16 * WF_DP + ks * 4];
-          ar[t] = mfma4(dv2.x, bv.x, ar[t]);
-          ar[t] = mfma4(-dv2.y, bv.y, ar[t]);
-          ai[t] = mfma4(dv2.x, bv.y, ai[t]);
-          ai[t] = mfma4(dv2.y, bv.x, ai[t]);
-        }
+        for (int t = 0; t < TPC; ++t)
+          cmac3(dsl[t * 16 * WF_DP + ks * 4], bv, bsum, ar[t], ai[t], a3[t]);
       }
       stage_d(sl ^ 1, c + 1);  // the next chunk into the slot chunk c - 1 used
       load_d(c + 2);
       __syncthreads();
     }
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) cmac3_finish(ar[t], ai[t], a3[t]);
 
     if constexpr (KIND == GK_FWD) {  // P_k = D_b R_k -> batch spectra
 #pragma unroll
@@ -763,18 +788,19 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks)
       if (!d_ok(ks * 4 + lq, r)) dc[ks] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) dc[ks].y = -dc[ks].y;  // conj D
 #pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
       floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+      floatx4 t3 = floatx4{0.f, 0.f, 0.f, 0.f};
       const float2* res = s_res + lq * WF_RP + nt * 16 + lr;
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
         const float2 sv = res[ks * 4 * WF_RP];
-        re = mfma4(dc[ks].x, sv.x, re);
-        re = mfma4(dc[ks].y, sv.y, re);
-        im = mfma4(dc[ks].x, sv.y, im);
-        im = mfma4(-dc[ks].y, sv.x, im);
+        cmac3(dc[ks], sv, sv.x + sv.y, re, im, t3);
       }
+      cmac3_finish(re, im, t3);
       const int blk = blk0 + nt;
       if (blk < a.nvb) {
         const int rb = mt * 16 + lq * 4;
