@@ -401,11 +401,12 @@ def add_practical(roof, practical, ms):
         roof["traffic_frac_of_practical"] = roof["traffic_gbs"] / practical
 
 
-def fp32_mfma_share(nb, fused=True):
+def fp32_mfma_share(nb, nr, fused=True):
     """Executed MFMA flops of the float32 products over the algorithmic 8 flops per complex
-    multiply-add: the persistent fused kernel (at most 16 batch rows) issues four real
-    16x16x4 products per complex one, the tiled and warp-specialised kernels three."""
-    return 1.0 if fused and nb <= 16 else 0.75
+    multiply-add: the persistent fused kernel (at most 16 batch rows, at most 224
+    receivers) issues four real 16x16x4 products per complex one, the tiled and
+    warp-specialised kernels three."""
+    return 1.0 if fused and nb <= 16 and nr <= 224 else 0.75
 
 
 def copy_calibration(mib, dev):
@@ -506,7 +507,7 @@ def bench_autograd(args, dev):
                      "traffic_unit": "HBM bytes per evaluation (counters, both launches)",
                      "algorithmic_flops": 16.0 * max(wl.nb_sweep) * wl.nr * wl.nvs * wl.nf,
                      "executed_mfma_flops": 16.0 * max(wl.nb_sweep) * wl.nr * wl.nvs * wl.nf *
-                     fp32_mfma_share(max(wl.nb_sweep), fused=False)},
+                     fp32_mfma_share(max(wl.nb_sweep), wl.nr, fused=False)},
         "reciprocity": rec,
         "by_batch": by_batch,
     }
@@ -627,7 +628,7 @@ def main():
                     "traffic": stored_traffic(args.workload, "gemm_fp32"),
                     "traffic_unit": "HBM bytes per launch (counters)",
                     "algorithmic_flops": gemm_flops,
-                    "executed_mfma_flops": gemm_flops * fp32_mfma_share(nb)}
+                    "executed_mfma_flops": gemm_flops * fp32_mfma_share(nb, wl.nr)}
     else:
         roof_ms = upd_ms
         roofline = {"kernel": f"update (inverse FFT + mask + {wl.optimizer} + model FFT)",
@@ -653,7 +654,7 @@ def main():
         # float32; for the split forms each of the three hi/lo products is required work.
         split = form in ("bf16x3", "fp16x3")
         counted = gemm_flops * (3 if split else 1)
-        hw = gemm_flops * (3 if split else fp32_mfma_share(nb))   # what the MFMA units execute
+        hw = gemm_flops * (3 if split else fp32_mfma_share(nb, wl.nr))   # what the MFMA units execute
         tr = stored_traffic(args.workload, f"gemm_{form}")
         return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
                 "counted_tflops": counted / (ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS[form],
