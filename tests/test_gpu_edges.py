@@ -233,3 +233,27 @@ def test_fp32_operators_large_batches(nb):
     v = synth.random_arrays(nb, (nb, nvs, nt))[0]
     gg = plan.mdc_adjoint(T(v), T(idx, torch.int32))
     assert relerr(H(gg), freq.mdc_adjoint(d[idx[ok]], f32(v)[ok], nf)) <= 1e-5
+
+
+@pytest.mark.parametrize("nb,nr", [(9, 257), (16, 300), (24, 300), (32, 131)])
+def test_fp32_tiled_products(nb, nr):
+    """The tiled fp32 kernel (three real products per complex multiply-add) where the
+    persistent one does not apply: batches of at most 16 over more than 224 receivers, and
+    17..32 rows over several receiver chunks.  Fused with the mask and a rejected index,
+    then the forward and adjoint operators alone."""
+    ns, nvs, nt, nf = 40, 37, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + nr + 5)
+    onset = synth.onsets(synth.WORKLOADS["tiny2d"].replace(dt=0.002), nr, nvs)
+    plan = make_plan(d, u, onset=onset, nb_max=nb, nf=nf)
+    good = batch(ns, nb, seed=nb)
+    idx = good.copy()
+    idx[-1] = ns + 1              # rejected: a source with zero wavefields
+    good = good[:-1]
+    G, loss, _ = plan.mdd_stoch_grad(T(r), T(idx.astype(np.int32), torch.int32))
+    lo, go = freq.batch_loss_grad(d, r, u, good, nf)
+    assert relerr(H(G), optim.apply_mask(go, onset)) <= 1e-5
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    ops = make_plan(d, u, nb_max=nb, nf=nf)
+    it = T(good.astype(np.int32), torch.int32)
+    assert relerr(H(ops.mdc_forward(T(r), it)), freq.mdc(d[good], r, nf)) <= 1e-5
+    assert relerr(H(ops.mdc_adjoint(T(u[good]), it)), freq.mdc_adjoint(d[good], u[good], nf)) <= 1e-5
