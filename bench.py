@@ -60,7 +60,8 @@ AUTOGRAD_TEXT = ("diff301: differentiation form, ns=nr=nvs=301 (10 m line), nt=1
 # Model-sized float32 arrays each update reads and writes (R and the optimiser state).
 STATE_ARRAYS = {"adam": 3, "nsgd": 2, "sgd": 1}
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6, "bf16": 2516.6}
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp32_cgemm": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6,
+                    "bf16": 2516.6}
 TRAFFIC_FILE = {w: os.path.join(ROOT, "profiles", f"traffic_{w}.md")
                 for w in list(WORKLOAD_TEXT) + ["diff301"]}
 CSRC = os.path.join(ROOT, "paper_2202_04486_amd", "csrc")
@@ -523,7 +524,10 @@ def main():
     ap.add_argument("--workload", default="line2d", choices=list(WORKLOAD_TEXT) + ["diff301"],
                     help="line2d (default, the headline), the 1600-trace 3D patch, or either "
                          "with a single virtual source")
-    ap.add_argument("--forms", default="fp32,bf16x3,fp16x3")
+    ap.add_argument("--forms", default=None,
+                    help="precision forms to time (default: fp32,bf16x3,fp16x3, and at the 3D "
+                         "patch also fp32_cgemm, the float32 products with four real products "
+                         "per complex one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stream-kernel", action="store_true",
                     help="also time the steps with the kernel streamed from pinned host memory")
@@ -570,6 +574,8 @@ def main():
     torch.cuda.synchronize()
     copy_calibration(args.copy_calibration_mib, dev)
 
+    if args.forms is None:
+        args.forms = "fp32,fp32_cgemm,bf16x3,fp16x3" if args.workload == "patch3d" else "fp32,bf16x3,fp16x3"
     forms = [f for f in args.forms.split(",") if f]
     if "fp32" not in forms:
         forms.insert(0, "fp32")
@@ -654,7 +660,8 @@ def main():
         # float32; for the split forms each of the three hi/lo products is required work.
         split = form in ("bf16x3", "fp16x3")
         counted = gemm_flops * (3 if split else 1)
-        hw = gemm_flops * (3 if split else fp32_mfma_share(nb, wl.nr))   # what the MFMA units execute
+        hw = gemm_flops * (3 if split else 1 if form == "fp32_cgemm" else
+                           fp32_mfma_share(nb, wl.nr))                 # what the MFMA units execute
         tr = stored_traffic(args.workload, f"gemm_{form}")
         return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
                 "counted_tflops": counted / (ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS[form],
@@ -689,6 +696,12 @@ def main():
                       "gemm_speedup_vs_fp32": per_launch(fp["prof"], "gemm") /
                       max(per_launch(res[f]["prof"], "gemm"), 1e-12)} for f in forms},
     }
+    if "fp32_cgemm" in res:   # the precision forms against the plain complex-GEMM float32 form
+        cg = res["fp32_cgemm"]
+        for f in forms:
+            out["forms"][f]["speedup_vs_fp32_cgemm"] = cg["elapsed"] / res[f]["elapsed"]
+            out["forms"][f]["gemm_speedup_vs_fp32_cgemm"] = (
+                per_launch(cg["prof"], "gemm") / max(per_launch(res[f]["prof"], "gemm"), 1e-12))
     if not args.no_full_gradient:
         log("timing full-gradient iterations")
         it_ms = time_full_gradient(wl, d, u, onset_t, dev, iters=5 if args.workload == "line2d" else 2)

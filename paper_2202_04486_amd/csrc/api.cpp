@@ -66,7 +66,7 @@ mdd_status check_dims(const mdd_dims* d) {
   if (!valid_nt(d->nt)) return MDD_ESHAPE;
   if (d->nf > d->nt / 2 + 1) return MDD_ESHAPE;
   if (d->nb_max > d->ns || d->nb_max > NB_LIMIT) return MDD_ESHAPE;
-  if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_BF16) return MDD_EUNSUPPORTED;
+  if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_FP32_CGEMM) return MDD_EUNSUPPORTED;
   if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD | MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
   // the full gradient visits every source: it needs the resident kernel spectra
   if ((d->flags & MDD_FLAG_FULL_GRAD) && (d->flags & MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;

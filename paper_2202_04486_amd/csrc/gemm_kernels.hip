@@ -14,7 +14,7 @@
 //       stays in LDS between the two products.  Every kind and precision.
 //   k_gemm_pipe   fp32, fused, nb <= 16, nr <= PIPE_KC: persistent, the next
 //       item's R_k in flight during the current item's products.
-//   k_gemm_ws<kind>  fp32, 33 <= nb <= 64, every kind: loader waves stream R_k
+//   k_gemm_ws<kind, prec>  fp32, 33 <= nb <= 64, every kind: loader waves stream R_k
 //       through an LDS ring for the compute waves; the adjoint needs no barrier
 //       (the adjoint kind reads the batch spectra into the residual planes).
 // R_k is read and G_k written exactly once.  G_k goes over R_k, or (the full
@@ -24,6 +24,9 @@
 // (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br) on v_mfma_f32_16x16x4_f32, or, in
 // the split-precision forms, on v_mfma_f32_16x16x32_{bf16,f16} with each
 // operand split into hi + lo and hi*hi + hi*lo + lo*hi accumulated in fp32.
+// The float32 tiled and warp-specialised kernels use three real products
+// instead (cmac3) unless the precision is MDD_PREC_FP32_CGEMM; the persistent
+// kernel keeps four.
 #include "device_common.h"
 #include "mdd_internal.h"
 
@@ -59,6 +62,30 @@ __device__ __forceinline__ void cmac3_finish(floatx4& t1, floatx4& t2, const flo
     t2[e] = x + t3[e];
   }
 }
+
+// Float32 complex multiply-add in the form the precision asks for: three real
+// products (cmac3, accumulators t1 t2 t3) for MDD_PREC_FP32, or the four of a plain
+// complex GEMM into (re, im) directly for MDD_PREC_FP32_CGEMM (t3 unused).
+template <int PREC>
+__device__ __forceinline__ void cmac(float2 av, float2 bv, float bsum, floatx4& re, floatx4& im,
+                                     floatx4& t3) {
+  if constexpr (PREC == MDD_PREC_FP32) {
+    cmac3(av, bv, bsum, re, im, t3);
+  } else {
+    re = mfma4(av.x, bv.x, re);
+    re = mfma4(-av.y, bv.y, re);
+    im = mfma4(av.x, bv.y, im);
+    im = mfma4(av.y, bv.x, im);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void cmac_finish(floatx4& re, floatx4& im, const floatx4& t3) {
+  if constexpr (PREC == MDD_PREC_FP32) cmac3_finish(re, im, t3);
+}
+
+template <int PREC>
+constexpr bool is_fp32() { return PREC == MDD_PREC_FP32 || PREC == MDD_PREC_FP32_CGEMM; }
 
 // Operand of a 16x16x32 split-precision MFMA: 8 consecutive k values of one
 // row (A) or one column (B), real and imaginary parts, hi and lo.
@@ -155,7 +182,7 @@ struct GemmCfg {
   static constexpr int S = TILES >= 4 ? 1 : 4 / TILES;  // waves splitting K
   static constexpr int G = 4 / S;                     // wave groups over tiles
   static constexpr int TPWV = TILES / G;              // tiles per wave
-  static constexpr bool SPLIT = PREC != MDD_PREC_FP32;
+  static constexpr bool SPLIT = !is_fp32<PREC>();
   static constexpr int KSTEP = SPLIT ? 32 : 4;        // receivers per MFMA
   static constexpr int KCMAX = NBT == 1 ? (SPLIT ? 256 : 224) : (NBT == 2 ? 128 : 64);  // receiver chunk
   static constexpr int KSW = KCMAX / KSTEP / S;       // k-steps per wave per chunk
@@ -345,8 +372,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
           for (int t = 0; t < C::TPWV; ++t) {
             const int mt = (g + t * C::G) / TNB;
-            cmac3(s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq], rv, rsum, acc_re[t], acc_im[t],
-                  acc_3[t]);
+            cmac<PREC>(s_d[(mt * 16 + lr) * C::DST + kk * 4 + lq], rv, rsum, acc_re[t], acc_im[t],
+                       acc_3[t]);
           }
         } else {
           using Op = SplitOp<PREC>;
@@ -384,7 +411,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
     if constexpr (!C::SPLIT) {
 #pragma unroll
-      for (int t = 0; t < C::TPWV; ++t) cmac3_finish(acc_re[t], acc_im[t], acc_3[t]);
+      for (int t = 0; t < C::TPWV; ++t) cmac_finish<PREC>(acc_re[t], acc_im[t], acc_3[t]);
     }
 
     // Residual (or predicted data) and the loss partial.
@@ -493,9 +520,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
           for (int kk = 0; kk < MB / 4; ++kk) {
             const float2 sv = s_res[(kk * 4 + lq) * C::RST + nt * 16 + lr];
-            cmac3(cconj(s_d[(kk * 4 + lq) * C::DST + mt * 16 + lr]), sv, sv.x + sv.y, re, im, t3);
+            cmac<PREC>(cconj(s_d[(kk * 4 + lq) * C::DST + mt * 16 + lr]), sv, sv.x + sv.y, re, im,
+                       t3);
           }
-          cmac3_finish(re, im, t3);
+          cmac_finish<PREC>(re, im, t3);
         } else {
           using Op = SplitOp<PREC>;
 #pragma unroll
@@ -555,7 +583,7 @@ constexpr int WF_DP = WF_KC + 4;              // D slot row pitch [b][r] (comple
 constexpr int WF_RP = 64 + 16;                // ring / residual row pitch [r or b][col]
 constexpr size_t WF_SMEM = sizeof(float2) * (2 * 64 * WF_DP + 2 * WF_KC * WF_RP);
 
-template <int KIND>
+template <int KIND, int PREC>
 __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
   constexpr int MB = 64, NW = 64, KC = WF_KC;
   constexpr int NCT = 64 * WF_CW, NLT = 64 * WF_LW;
@@ -633,7 +661,7 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
         *reinterpret_cast<float4*>(s_d + sl * DSL + b * WF_DP + rr) = v;
       }
     };
-    // three real products per complex multiply-add (see cmac3): t1, t2, t3 per tile
+    // per tile: (re, im) and the third accumulator of cmac3 (unused by the cgemm form)
     floatx4 ar[TPC], ai[TPC], a3[TPC];
 #pragma unroll
     for (int t = 0; t < TPC; ++t) {
@@ -657,14 +685,14 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
         const float bsum = bv.x + bv.y;
 #pragma unroll
         for (int t = 0; t < TPC; ++t)
-          cmac3(dsl[t * 16 * WF_DP + ks * 4], bv, bsum, ar[t], ai[t], a3[t]);
+          cmac<PREC>(dsl[t * 16 * WF_DP + ks * 4], bv, bsum, ar[t], ai[t], a3[t]);
       }
       stage_d(sl ^ 1, c + 1);  // the next chunk into the slot chunk c - 1 used
       load_d(c + 2);
       __syncthreads();
     }
 #pragma unroll
-    for (int t = 0; t < TPC; ++t) cmac3_finish(ar[t], ai[t], a3[t]);
+    for (int t = 0; t < TPC; ++t) cmac_finish<PREC>(ar[t], ai[t], a3[t]);
 
     if constexpr (KIND == GK_FWD) {  // P_k = D_b R_k -> batch spectra
 #pragma unroll
@@ -798,9 +826,9 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
 #pragma unroll
       for (int ks = 0; ks < 16; ++ks) {
         const float2 sv = res[ks * 4 * WF_RP];
-        cmac3(dc[ks], sv, sv.x + sv.y, re, im, t3);
+        cmac<PREC>(dc[ks], sv, sv.x + sv.y, re, im, t3);
       }
-      cmac3_finish(re, im, t3);
+      cmac_finish<PREC>(re, im, t3);
       const int blk = blk0 + nt;
       if (blk < a.nvb) {
         const int rb = mt * 16 + lq * 4;
@@ -985,12 +1013,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   if (tid == 0) a.loss_part[start] = tot;
 }
 
-template <int KIND>
+template <int KIND, int PREC>
 hipError_t launch_ws(const GemmArgs& a, hipStream_t s) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_ws<KIND>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_ws<KIND, PREC>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)WF_SMEM);
   const int ncg = (a.nvb + 3) / 4;
-  hipLaunchKernelGGL(k_gemm_ws<KIND>, dim3(a.nf * ncg), dim3(WF_THREADS), WF_SMEM, s, a);
+  hipLaunchKernelGGL((k_gemm_ws<KIND, PREC>), dim3(a.nf * ncg), dim3(WF_THREADS), WF_SMEM, s, a);
   return hipGetLastError();
 }
 
@@ -1027,7 +1055,7 @@ hipError_t launch_cfg(int kind, const GemmArgs& a, hipStream_t s) {
 
 template <int PREC>
 hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
-  if constexpr (PREC == MDD_PREC_FP32) {
+  if constexpr (is_fp32<PREC>()) {  // four real products per complex one in this kernel
     if (kind == GK_FUSED && a.nb <= 16 && a.nr <= PIPE_KC) {
       const int total = a.nf * a.nvb;
       int grid = total < PIPE_WGS ? total : PIPE_WGS;
@@ -1045,11 +1073,11 @@ hipError_t launch_prec(int kind, const GemmArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;  // not reached: nb > 16 went to launch_gemm_split
   } else {
     if (a.nb <= 32) return launch_cfg<PREC, 2, 2>(kind, a, s);
-    if constexpr (PREC == MDD_PREC_FP32) {
+    if constexpr (is_fp32<PREC>()) {
       switch (kind) {
-        case GK_FUSED: return launch_ws<GK_FUSED>(a, s);
-        case GK_FWD: return launch_ws<GK_FWD>(a, s);
-        case GK_ADJ: return launch_ws<GK_ADJ>(a, s);
+        case GK_FUSED: return launch_ws<GK_FUSED, PREC>(a, s);
+        case GK_FWD: return launch_ws<GK_FWD, PREC>(a, s);
+        case GK_ADJ: return launch_ws<GK_ADJ, PREC>(a, s);
         default: return hipErrorInvalidValue;
       }
     }
@@ -1066,6 +1094,7 @@ hipError_t launch_gemm(int kind, int precision, const GemmArgs& a, hipStream_t s
     case MDD_PREC_BF16X3: return launch_prec<MDD_PREC_BF16X3>(kind, a, s);
     case MDD_PREC_FP16X3: return launch_prec<MDD_PREC_FP16X3>(kind, a, s);
     case MDD_PREC_BF16: return launch_prec<MDD_PREC_BF16>(kind, a, s);
+    case MDD_PREC_FP32_CGEMM: return launch_prec<MDD_PREC_FP32_CGEMM>(kind, a, s);
     default: return hipErrorInvalidValue;
   }
 }

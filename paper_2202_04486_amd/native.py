@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libm
 
 MDD_OK, MDD_EINVAL, MDD_ESHAPE, MDD_ENOMEM, MDD_EHIP, MDD_EUNSUPPORTED, MDD_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
-PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3}
+PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3, "fp32_cgemm": 4}
 FLAG_STORE_RF = 1
 FLAG_FULL_GRAD = 2
 FLAG_STREAM_KERNEL = 4

@@ -38,7 +38,8 @@ class Plan:
 
     ns sources, nr receivers, nvs virtual sources, nt time samples, nf retained
     one-sided frequency bins, nb_max the largest batch; precision one of
-    'fp32', 'bf16x3', 'fp16x3', 'bf16'."""
+    'fp32', 'bf16x3', 'fp16x3', 'bf16' (single pass, diagnostic) and 'fp32_cgemm'
+    (float32 with four real products per complex one, for comparison)."""
 
     def __init__(self, ns, nr, nvs, nt, nf, nb_max, precision="fp32", store_rf=False,
                  device=None, full_grad=False, stream_kernel=False):

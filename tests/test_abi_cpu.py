@@ -48,6 +48,12 @@ def dims(**kw):
     return native.make_dims(**base)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3", "bf16", "fp32_cgemm"])
+def test_every_precision_accepted(lib, prec):
+    """Every precision setting plans on the same workspace as float32."""
+    assert native.workspace_bytes(dims(precision=prec)) == native.workspace_bytes(dims())
+
+
 def test_workspace_bytes_valid_and_monotone(lib):
     a = native.workspace_bytes(dims())
     b = native.workspace_bytes(dims(nvs=40))
@@ -72,7 +78,8 @@ def test_streamed_kernel_flag_keeps_only_the_batch_rows(lib):
 
 @pytest.mark.parametrize("kw", [dict(nf=66), dict(nt=100), dict(nt=2048), dict(nb_max=33),
                                 dict(ns=100, nb_max=65), dict(ns=0), dict(nr=-1), dict(nf=0),
-                                dict(precision=7), dict(flags=8), dict(flags=6), dict(nvs=5000)])
+                                dict(precision=5), dict(precision=-1), dict(flags=8), dict(flags=6),
+                                dict(nvs=5000)])
 def test_invalid_dims_rejected(lib, kw):
     assert native.workspace_bytes(dims(**kw)) == 0
     out = ctypes.c_void_p()

@@ -257,3 +257,22 @@ def test_fp32_tiled_products(nb, nr):
     it = T(good.astype(np.int32), torch.int32)
     assert relerr(H(ops.mdc_forward(T(r), it)), freq.mdc(d[good], r, nf)) <= 1e-5
     assert relerr(H(ops.mdc_adjoint(T(u[good]), it)), freq.mdc_adjoint(d[good], u[good], nf)) <= 1e-5
+
+
+@pytest.mark.parametrize("nb,nr", [(9, 257), (24, 300), (47, 131), (64, 90)])
+def test_fp32_cgemm_form(nb, nr):
+    """The comparison precision MDD_PREC_FP32_CGEMM (four real products per complex one in
+    every kernel) through the tiled kernels (batches of 9 over 257 receivers, 24 rows) and
+    the warp-specialised ones (47 and 64 rows): the fused gradient and the two operators
+    alone against the oracle."""
+    ns, nvs, nt, nf = 70, 45, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb * 3 + nr)
+    idx = batch(ns, nb, seed=nb)
+    it = T(idx, torch.int32)
+    plan = make_plan(d, u, nb_max=nb, nf=nf, precision="fp32_cgemm")
+    G, loss, _ = plan.mdd_stoch_grad(T(r), it)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= 1e-5
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    assert relerr(H(plan.mdc_forward(T(r), it)), freq.mdc(d[idx], r, nf)) <= 1e-5
+    assert relerr(H(plan.mdc_adjoint(T(u[idx]), it)), freq.mdc_adjoint(d[idx], u[idx], nf)) <= 1e-5
