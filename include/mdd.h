@@ -67,9 +67,9 @@ typedef int32_t mdd_status;
  * (nvs = 1) the products are matrix-vector products bound by the bytes of D_b and
  * run in float32 on the vector units whatever the setting (Appendix A: the
  * matrix-matrix product reduces to a matrix-vector product there). */
-#define MDD_PREC_FP32 0   /* float32 MFMA, float32 accumulate; the tiled and warp-specialised
-                             kernels (more than 16 batch rows, or more than 224 receivers)
-                             form each complex product from three real ones */
+#define MDD_PREC_FP32 0   /* float32 MFMA, float32 accumulate.  Each complex product is formed
+                             from three real ones, except in the fused gradient / step at
+                             most 16 batch rows over at most 224 receivers, which uses four */
 #define MDD_PREC_BF16X3 1 /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, float32 accumulate */
 #define MDD_PREC_FP16X3 2 /* fp16 hi+lo split with power-of-two tile scaling, float32 accumulate */
 #define MDD_PREC_BF16 3   /* single bf16 product (diagnostic: expected to miss 1e-3) */
