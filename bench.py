@@ -55,8 +55,9 @@ WORKLOAD_TEXT = {
 }
 DEFAULT_EPOCHS = {"line2d": 10, "patch3d": 1, "line2d_vs1": 50, "patch3d_vs1": 10}
 AUTOGRAD_TEXT = ("diff301: differentiation form, ns=nr=nvs=301 (10 m line), nt=1024, nf=257, "
-                 "loss 1/2 ||mdc(C_r z) - u_b||^2 through torch.autograd (mdc_forward / "
-                 "mdc_adjoint and the reciprocity kernel), random N(0,1) model, batches 8 / 32 / 64")
+                 "loss 1/2 ||P_b C_r z - u_b||^2 through torch.autograd (mdc_forward_rec / "
+                 "mdc_adjoint_rec: C_r on the spectra inside the operators), random N(0,1) "
+                 "model, batches 8 / 32 / 64")
 # Model-sized float32 arrays each update reads and writes (R and the optimiser state).
 STATE_ARRAYS = {"adam": 3, "nsgd": 2, "sgd": 1}
 HBM_PEAK_GBS = 8000.0
@@ -423,14 +424,16 @@ def copy_calibration(mib, dev):
 
 
 def bench_autograd(args, dev):
-    """Differentiation form: one gradient of 1/2 ||mdc(C_r z) - u_b||^2 with respect to
-    z through torch.autograd, whose backward runs the adjoint kernel and the reciprocity
-    kernel again.  Timed per batch size; kernel times from the plan's HIP events over
-    separate evaluations; the reciprocity kernel timed on its own."""
+    """Differentiation form: one gradient of 1/2 ||P_b C_r z - u_b||^2 with respect to z
+    through torch.autograd.  The operator P_b C_r is mdc_rec (C_r applied to the spectra
+    inside mdc_forward_rec, and C_r P_b^H in mdc_adjoint_rec for the backward).  Timed per
+    batch size; kernel times from the plan's HIP events over separate evaluations; at the
+    largest batch also mdc(reciprocity(z)), C_r as its own kernel on the traces, which is
+    timed on its own as well."""
     import torch
 
     import synth
-    from paper_2202_04486_amd.autograd import _reciprocity, mdc, reciprocity
+    from paper_2202_04486_amd.autograd import _reciprocity, mdc, mdc_rec, reciprocity
     from paper_2202_04486_amd.plan import Plan
     wl = synth.WORKLOADS["diff301"]
     log("generating inputs")
@@ -449,9 +452,9 @@ def bench_autograd(args, dev):
     for nb in wl.nb_sweep:
         idx_tab, lens, _ = step_tables(wl, nb, W + 2 * K, dev)
 
-        def ev(j):
+        def ev(j, fused=True):
             idx = idx_tab[j, :lens[j]]
-            pred = mdc(reciprocity(z), idx, plan)
+            pred = mdc_rec(z, idx, plan) if fused else mdc(reciprocity(z), idx, plan)
             loss = 0.5 * ((pred - u.index_select(0, idx.long())) ** 2).sum()
             return torch.autograd.grad(loss, z)[0]
 
@@ -475,6 +478,14 @@ def bench_autograd(args, dev):
                         "kernel_ms_per_eval": {k: v[0] / K for k, v in prof.items() if v[1]},
                         "products_tflops": flops / (gemm_ms * 1e-3) / 1e12,
                         "products_mfma_frac": flops / (gemm_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+        if nb == max(wl.nb_sweep):   # the same evaluations with C_r as a kernel on the traces
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(W, W + K):
+                ev(j, fused=False)
+            torch.cuda.synchronize()
+            by_batch[nb]["unfused_ms_per_eval"] = 1e3 * (time.perf_counter() - t0) / K
+            by_batch[nb]["unfused_note"] = "mdc(reciprocity(z)): mdd_reciprocity on the traces"
     # the reciprocity kernel alone: z read once, the result written once
     zz = z.detach()
     for _ in range(3):
@@ -492,6 +503,20 @@ def bench_autograd(args, dev):
            "achieved": rec_bytes / (rec_ms * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS,
            "frac": rec_bytes / (rec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     add_practical(rec, practical_hbm_gbs(dev), rec_ms)
+    # C_r on the spectra alone (the model spectra of one mdc_forward_rec), by the plan's events
+    plan.profile_enable(True, capacity=64)
+    idx_last = idx_tab[0, :lens[0]]
+    for _ in range(10):
+        plan.mdc_forward_rec(zz, idx_last)
+    srec = plan.profile_read()["reciprocity"]
+    plan.profile_enable(False)
+    srec_ms = srec[0] / max(srec[1], 1)
+    srec_bytes = 2 * 8.0 * wl.nr * wl.nvs * wl.nf
+    rec["spectral"] = {"ms": srec_ms, "algorithmic_bytes": srec_bytes,
+                       "traffic": stored_traffic("diff301", "spec_reciprocity"),
+                       "achieved": srec_bytes / (srec_ms * 1e-3) / 1e9, "unit": "GB/s",
+                       "frac": srec_bytes / (srec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "note": "C_r on the nr x nvs x nf retained spectra, read and written once"}
     top = by_batch[max(wl.nb_sweep)]
     out = {
         "metric": METRIC, "value": top["value"], "unit": "grad evals/s", "n_gpus": 1, "steps": K,

@@ -159,6 +159,19 @@ mdd_status mdc_forward(mdd_plan* plan, const float* R, const int32_t* idx, int32
 mdd_status mdc_adjoint(mdd_plan* plan, const float* V, const int32_t* idx, int32_t nb,
                        float* G_out);
 
+/* The same operators with the reciprocity preconditioner C_r of the preconditioned
+ * functional (Theory section; C_r R = (R + R^T) / 2 over receiver and virtual source):
+ *   mdc_forward_rec: U_out = P+_b C_r R;    mdc_adjoint_rec: G_out = C_r P+_b^H V.
+ * C_r is applied to the retained spectra of R (after its transform) or of the adjoint
+ * product (before the inverse transform), which equals applying it to the traces since
+ * the transform acts on each trace alone; it reads and writes nr * nvs * nf complex
+ * values instead of the traces.  Needs nr == nvs (MDD_ESHAPE otherwise) and
+ * mdd_set_kernel; arguments, layouts and errors as for mdc_forward / mdc_adjoint. */
+mdd_status mdc_forward_rec(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
+                           float* U_out);
+mdd_status mdc_adjoint_rec(mdd_plan* plan, const float* V, const int32_t* idx, int32_t nb,
+                           float* G_out);
+
 /* Mini-batch gradient of the finite-sum functional (Theory section):
  *   loss = 1/2 sum_{b} || p-_{idx[b]} - P+_{idx[b]} R ||^2        (float64)
  *   G    = C_c [ - sum_{b} P+_{idx[b]}^H (p-_{idx[b]} - P+_{idx[b]} R) ]
@@ -246,7 +259,8 @@ mdd_status mdd_sigma_max2(mdd_plan* plan, int32_t iters, double* lam_out);
 #define MDD_KC_UPDATE 2      /* inverse transform + mask + update (+ model transform) */
 #define MDD_KC_REDUCE 3      /* float64 reductions */
 #define MDD_KC_DATA_FFT 4    /* transforms of batch data (forward / adjoint operators) */
-#define MDD_KC_COUNT 5
+#define MDD_KC_RECIPROCITY 5 /* C_r on spectra (mdc_forward_rec / mdc_adjoint_rec) */
+#define MDD_KC_COUNT 6
 mdd_status mdd_profile_enable(mdd_plan* plan, int32_t enable, int32_t capacity);
 mdd_status mdd_profile_read(mdd_plan* plan, double* ms_host, int64_t* count_host);
 

@@ -71,3 +71,28 @@ def reciprocity(z: torch.Tensor) -> torch.Tensor:
     """Reciprocity preconditioner C_r z = (z + z^T)/2 over (receiver, virtual source),
     in-graph (Theory section, preconditioned functional); self-adjoint."""
     return Reciprocity.apply(z)
+
+
+class MDCRec(torch.autograd.Function):
+    """U_b = P+_b C_r z in one operator (mdc_forward_rec); the backward is C_r P+_b^H
+    (mdc_adjoint_rec).  The same value as mdc(reciprocity(z)), with C_r applied to the
+    retained spectra inside the operator instead of to the traces."""
+
+    @staticmethod
+    def forward(ctx, z: torch.Tensor, idx: torch.Tensor, plan: Plan):
+        ctx.plan = plan
+        ctx.save_for_backward(idx)
+        return plan.mdc_forward_rec(z.contiguous(), idx)
+
+    @staticmethod
+    def backward(ctx, grad_u: torch.Tensor):
+        (idx,) = ctx.saved_tensors
+        grad_z = None
+        if ctx.needs_input_grad[0]:
+            grad_z = ctx.plan.mdc_adjoint_rec(grad_u.contiguous(), idx)
+        return grad_z, None, None
+
+
+def mdc_rec(z: torch.Tensor, idx: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable U_b = P+_b C_r z (nr == nvs) for the batch `idx`."""
+    return MDCRec.apply(z, idx, plan)

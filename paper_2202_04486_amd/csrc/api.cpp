@@ -480,6 +480,49 @@ mdd_status mdc_adjoint(mdd_plan* p, const float* V, const int32_t* idx, int32_t 
   return p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_IRFFT, b, p->stream); });
 }
 
+// C_r on the plan's model / gradient spectra (nr = nvs; identity for a single trace).
+static mdd_status spec_reciprocity(mdd_plan* p) {
+  if (p->d.nr == 1) return MDD_OK;
+  const TraceArgs a = p->blocked(p->F(), p->d.nr);
+  return p->run(MDD_KC_RECIPROCITY, [&] {
+    return launch_spec_reciprocity(p->F(), p->d.nr, p->d.nf, a.s_row, a.s_cb, p->stream);
+  });
+}
+
+mdd_status mdc_forward_rec(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb,
+                           float* U_out) {
+  if (!p || !R || !idx || !U_out) return MDD_EINVAL;
+  if (p->d.nr != p->d.nvs) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
+  if (!p->kernel_set) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  MDD_TRY(p->model_fft(R, nullptr, 0.0));
+  MDD_TRY(spec_reciprocity(p));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->products(GK_FWD, g));
+  TraceArgs a = p->blocked(p->Bsp(), nb);
+  a.x_out = U_out;
+  return p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_IRFFT, a, p->stream); });
+}
+
+mdd_status mdc_adjoint_rec(mdd_plan* p, const float* V, const int32_t* idx, int32_t nb,
+                           float* G_out) {
+  if (!p || !V || !idx || !G_out) return MDD_EINVAL;
+  if (p->d.nr != p->d.nvs) return MDD_ESHAPE;
+  MDD_TRY(p->batch_ok(nb));
+  if (!p->kernel_set) return MDD_ESTATE;
+  p->spec_model = nullptr;
+  TraceArgs a = p->blocked(p->Bsp(), nb);
+  a.x_in = V;
+  MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
+  const GemmArgs g = p->gemm(idx, nb);
+  MDD_TRY(p->products(GK_ADJ, g));
+  MDD_TRY(spec_reciprocity(p));
+  TraceArgs b = p->blocked(p->F(), p->d.nr);
+  b.x_out = G_out;
+  return p->run(MDD_KC_UPDATE, [&] { return launch_trace(TM_IRFFT, b, p->stream); });
+}
+
 mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32_t nb,
                           float* G_out, double* loss_out, double* gnorm2_out) {
   if (!p || !R || !idx || !G_out) return MDD_EINVAL;

@@ -111,6 +111,8 @@ hipError_t launch_row_sum(const double* part, int rows, int cols, double scale, 
                           hipStream_t s);
 hipError_t launch_iota(int32_t* out, int n, hipStream_t s);
 hipError_t launch_reciprocity(const float* z, float* out, int n, int nt, hipStream_t s);
+hipError_t launch_spec_reciprocity(float2* X, int n, int nf, long long s_row, long long s_cb,
+                                   hipStream_t s);
 hipError_t launch_freq_absmax(const float2* Df, int nf, long long count, long long stride,
                               float* out, hipStream_t s);
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,

@@ -171,6 +171,43 @@ __global__ __launch_bounds__(256) void k_reciprocity(const float* z, float* out,
   }
 }
 
+// C_r on blocked spectra (nr = nvs = n): X(r, vs, k) <- (X(r, vs, k) + X(vs, r, k)) / 2 for
+// every retained bin k, which equals the spectra of C_r applied to the traces (the time
+// transform acts on each trace alone).  Element (r, vs, k) sits at
+// r * s_row + (vs / 16) * s_cb + k * 16 + vs % 16.  Workgroup (pair, k) takes the 16 x 16
+// tiles (I, J) and (J, I), I <= J, of bin k: both are read, transposed through LDS, and
+// the average is written to both (a diagonal tile is its own mirror).  Receivers and
+// columns at or beyond n are left alone.
+__global__ __launch_bounds__(256) void k_spec_reciprocity(float2* X, int n, long long s_row,
+                                                          long long s_cb, int ntile) {
+  __shared__ float2 s_b[16][17];
+  int p = blockIdx.x, I = 0;
+  while (p >= ntile - I) {  // pair index -> (I, J), I <= J, row-major over the triangle
+    p -= ntile - I;
+    ++I;
+  }
+  const int J = I + p;
+  const int k = blockIdx.y;
+  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+  const int ra = I * 16 + i, ca = J * 16 + j;  // element of tile (I, J)
+  const int rb = J * 16 + i, cb = I * 16 + j;  // element of tile (J, I)
+  const bool oka = ra < n && ca < n, okb = rb < n && cb < n;
+  float2* pa = X + (oka ? ra : 0) * s_row + (long long)J * s_cb + (long long)k * 16 + j;
+  float2* pb = X + (okb ? rb : 0) * s_row + (long long)I * s_cb + (long long)k * 16 + j;
+  const float2 a = oka ? *pa : make_float2(0.f, 0.f);
+  const float2 b = okb ? *pb : make_float2(0.f, 0.f);
+  s_b[i][j] = b;
+  __syncthreads();
+  // mirror of (ra, ca) = (I*16 + i, J*16 + j) is (J*16 + j, I*16 + i): element (j, i) of tile (J, I)
+  const float2 m = s_b[j][i];
+  const float2 v = make_float2((a.x + m.x) * 0.5f, (a.y + m.y) * 0.5f);
+  __syncthreads();
+  s_b[j][i] = v;  // the same value, as seen from tile (J, I)
+  __syncthreads();
+  if (oka) *pa = v;
+  if (okb && I != J) *pb = s_b[i][j];
+}
+
 // out[i] = i: the list of every source, batched in order by the full gradient.
 __global__ void k_iota(int32_t* out, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,6 +234,15 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 
 hipError_t launch_reciprocity(const float* z, float* out, int n, int nt, hipStream_t s) {
   hipLaunchKernelGGL(k_reciprocity, dim3(n, n), dim3(256), 0, s, z, out, n, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_reciprocity(float2* X, int n, int nf, long long s_row, long long s_cb,
+                                   hipStream_t s) {
+  const int ntile = (n + 15) / 16;
+  const int npair = ntile * (ntile + 1) / 2;
+  if (n < 1 || nf < 1 || nf > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_spec_reciprocity, dim3(npair, nf), dim3(256), 0, s, X, n, s_row, s_cb, ntile);
   return hipGetLastError();
 }
 

@@ -17,12 +17,12 @@ FLAG_STORE_RF = 1
 FLAG_FULL_GRAD = 2
 FLAG_STREAM_KERNEL = 4
 OPT = {"sgd": 0, "adam": 1, "nsgd": 2}
-KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft")
+KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft", "reciprocity")
 
 # Entry points the header declares (checked by the test-suite against the .so).
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
            "mdd_set_kernel", "mdd_stage_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward",
-           "mdc_adjoint",
+           "mdc_adjoint", "mdc_forward_rec", "mdc_adjoint_rec",
            "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
            "mdd_sigma_max2",
@@ -74,6 +74,8 @@ def load() -> ctypes.CDLL:
         "mdd_set_mask": (_I32, [_P, _P]),
         "mdc_forward": (_I32, [_P, _P, _P, _I32, _P]),
         "mdc_adjoint": (_I32, [_P, _P, _P, _I32, _P]),
+        "mdc_forward_rec": (_I32, [_P, _P, _P, _I32, _P]),
+        "mdc_adjoint_rec": (_I32, [_P, _P, _P, _I32, _P]),
         "mdd_stoch_grad": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
         "mdd_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _I32, _P, _P]),
         "mdd_full_grad": (_I32, [_P, _P, _P, _P, _P]),

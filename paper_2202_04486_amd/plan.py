@@ -119,23 +119,31 @@ class Plan:
         self._call("mdd_set_mask", _ptr(onset))
 
     # ---------------------------------------------------------------- operator
-    def mdc_forward(self, R, idx, out=None):
+    def mdc_forward(self, R, idx, out=None, entry="mdc_forward"):
         _need(R, "R", (self.nr, self.nvs, self.nt), torch.float32, self.device)
         nb = self._idx(idx)
         if out is None:
             out = torch.empty((nb, self.nvs, self.nt), dtype=torch.float32, device=self.device)
         _need(out, "U_out", (nb, self.nvs, self.nt), torch.float32, self.device)
-        self._call("mdc_forward", _ptr(R), _ptr(idx), nb, _ptr(out))
+        self._call(entry, _ptr(R), _ptr(idx), nb, _ptr(out))
         return out
 
-    def mdc_adjoint(self, V, idx, out=None):
+    def mdc_adjoint(self, V, idx, out=None, entry="mdc_adjoint"):
         nb = self._idx(idx)
         _need(V, "V", (nb, self.nvs, self.nt), torch.float32, self.device)
         if out is None:
             out = torch.empty((self.nr, self.nvs, self.nt), dtype=torch.float32, device=self.device)
         _need(out, "G_out", (self.nr, self.nvs, self.nt), torch.float32, self.device)
-        self._call("mdc_adjoint", _ptr(V), _ptr(idx), nb, _ptr(out))
+        self._call(entry, _ptr(V), _ptr(idx), nb, _ptr(out))
         return out
+
+    def mdc_forward_rec(self, R, idx, out=None):
+        """mdc_forward of C_r R (nr == nvs), with C_r applied to the spectra of R."""
+        return self.mdc_forward(R, idx, out, entry="mdc_forward_rec")
+
+    def mdc_adjoint_rec(self, V, idx, out=None):
+        """C_r of mdc_adjoint(V) (nr == nvs), with C_r applied to the adjoint's spectra."""
+        return self.mdc_adjoint(V, idx, out, entry="mdc_adjoint_rec")
 
     def _scalar(self, t, name):
         if t is None:

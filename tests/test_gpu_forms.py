@@ -210,3 +210,62 @@ def test_reciprocity_kernel_rejects_bad_arguments():
              lib.mdd_reciprocity(p, p, 4097, 128, s),
              lib.mdd_reciprocity(p, p, 4, 200, s)]
     assert codes == [native.MDD_EINVAL] * 2 + [native.MDD_ESHAPE] * 3
+
+
+@pytest.mark.parametrize("nb", [8, 32, 64])
+def test_mdc_rec_gradient_full_size(diff301, nb):
+    """The fused operator mdc_rec (C_r applied to spectra inside the library) at 301 traces:
+    the loss and the gradient through autograd against the oracle's gradient through C_r."""
+    from paper_2202_04486_amd.autograd import mdc_rec
+    wl, d, u, plan, z0, _, _ = diff301
+    idx = optim.batches(synth.epoch_permutations(wl, 1)[0], nb)[0]
+    it = T(idx, torch.int32)
+    z = T(z0).requires_grad_(True)
+    loss = 0.5 * ((mdc_rec(z, it, plan) - T(u[idx])).double() ** 2).sum()
+    loss.backward()
+    lo, go = freq.batch_loss_grad(d, optim.reciprocity(z0), u, idx, wl.nf)
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    assert relerr(H(z.grad), optim.reciprocity(go)) <= 1e-5
+
+
+def test_mdc_rec_dot_product(diff301):
+    """<P C_r z, y> = <z, C_r P^H y> for the fused pair, in float64 sums of float32 results."""
+    wl, d, u, plan, z0, v0, y0 = diff301
+    idx = optim.batches(synth.epoch_permutations(wl, 1)[0], 64)[0]
+    it = T(idx, torch.int32)
+    a = H(plan.mdc_forward_rec(T(z0), it))
+    b = H(plan.mdc_adjoint_rec(T(y0), it))
+    lhs, rhs = float(np.sum(a * y0)), float(np.sum(z0 * b))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,nt,nf,nb", [(1, 128, 65, 3), (17, 256, 100, 5), (37, 256, 129, 40)])
+def test_mdc_rec_operators_ragged(n, nt, nf, nb):
+    """mdc_forward_rec and mdc_adjoint_rec at trace counts that leave the last 16-column
+    block partial (and a single trace, where C_r is the identity), against the oracle and
+    against the separate reciprocity kernel plus the plain operators."""
+    from gpu_helpers import batch, make_plan, random_case
+    from paper_2202_04486_amd.autograd import _reciprocity
+    ns = max(nb + 3, 12)
+    d, u, r = random_case(ns, n, n, nt, seed=n + nb)
+    plan = make_plan(d, u, nb_max=nb, nf=nf)
+    idx = batch(ns, nb, seed=n)
+    it = T(idx, torch.int32)
+    fwd = plan.mdc_forward_rec(T(r), it)
+    assert relerr(H(fwd), freq.mdc(d[idx], optim.reciprocity(r), nf)) <= 1e-5
+    assert relerr(H(fwd), H(plan.mdc_forward(_reciprocity(T(r)), it))) <= 1e-6
+    adj = plan.mdc_adjoint_rec(T(u[idx]), it)
+    assert relerr(H(adj), optim.reciprocity(freq.mdc_adjoint(d[idx], u[idx], nf))) <= 1e-5
+    assert relerr(H(adj), H(_reciprocity(plan.mdc_adjoint(T(u[idx]), it)))) <= 1e-6
+
+
+def test_mdc_rec_needs_square_models():
+    from gpu_helpers import make_plan, random_case
+    from paper_2202_04486_amd import MddError
+    d, u, r = random_case(10, 12, 9, 128, seed=3)
+    plan = make_plan(d, u, nb_max=4, nf=65)
+    it = T(np.arange(4, dtype=np.int32), torch.int32)
+    with pytest.raises(MddError):
+        plan.mdc_forward_rec(T(r), it)
+    with pytest.raises(MddError):
+        plan.mdc_adjoint_rec(T(u[:4]), it)
