@@ -40,6 +40,6 @@ def test_committed_summaries_match_the_current_kernels():
     for workload, keys in (("line2d", ("update", "gemm_fp32")),
                            ("patch3d", ("update", "gemm_fp32", "gemm_bf16x3", "gemm_fp16x3")),
                            ("patch3d_vs1", ("update", "gemv")),
-                           ("diff301", ("products", "reciprocity"))):
+                           ("diff301", ("products", "reciprocity", "spec_reciprocity"))):
         for k in keys:
             assert bench.stored_traffic(workload, k) is not None, (workload, k)
