@@ -228,8 +228,8 @@ hipError_t launch_mq(int kind, const GemmArgs& a, hipStream_t s) {
 
 int gemv_groups(int nb, int nf) {
   const int most = (nb + 7) / 8;                 // at least 8 rows per group
-  int want = (3 * 256 + nf - 1) / nf;            // about three workgroups per CU
-  if (want < 1) want = 1;
+  int want = (3 * 256 + nf - 1) / nf;            // about three workgroups per CU,
+  if (want < 4) want = 4;                        // and at least four groups
   return want < most ? want : most;
 }
 
