@@ -334,6 +334,16 @@ def test_reciprocity_self_adjoint_idempotent():
     np.testing.assert_allclose(cz, np.swapaxes(cz, 0, 1), atol=0)
 
 
+def test_reciprocity_commutes_with_the_trace_transform():
+    """C_r acts on each time sample alone, so it can be applied to the retained spectra of
+    the model (or of the adjoint's output) instead of the traces: on every bin,
+    rfft(C_r z) = (Z + Z^T) / 2 with Z = rfft(z), so every retained band sees the same model."""
+    z = rand((7, 7, 16), 37)
+    Z = np.fft.rfft(z, axis=-1)
+    np.testing.assert_allclose(np.fft.rfft(optim.reciprocity(z), axis=-1),
+                               0.5 * (Z + np.swapaxes(Z, 0, 1)), atol=1e-13)
+
+
 # ---------------------------------------------------------------- updates
 
 def test_adam_constant_gradient_closed_form():
