@@ -117,7 +117,8 @@ def patch3d():
     return wl, d, r, u, onset, idx, cols, go
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16x3", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp32_cgemm", 1e-5), ("bf16x3", 1e-3),
+                                      ("fp16x3", 1e-3)])
 def test_patch3d_gradient_sampled_columns(patch3d, prec, tol):
     from paper_2202_04486_amd.plan import Plan
     wl, d, r, u, onset, idx, cols, go = patch3d

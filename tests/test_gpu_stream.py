@@ -135,3 +135,18 @@ def test_streamed_epoch_from_pinned_host_memory(opt, store_rf):
         states.append((R, m, v, losses))
     for x, y in zip(*states):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("nb", [9, 64])
+def test_staged_reciprocity_operators_equal_resident(nb):
+    """mdc_forward_rec / mdc_adjoint_rec (C_r on spectra, nr == nvs) with the kernel rows
+    staged per batch: bitwise the resident plan's results."""
+    ns, n, nt, nf = 70, 40, 256, 100
+    d, u, r = random_case(ns, n, n, nt, seed=nb + 3)
+    res = make_plan(d, u, nb_max=nb, nf=nf)
+    st = streamed_plan(d, u, nb, nf)
+    idx = batch(ns, nb, seed=nb + 1)
+    it = T(idx, torch.int32)
+    st.mdd_stage_kernel(T(d[idx]))
+    assert torch.equal(res.mdc_forward_rec(T(r), it), st.mdc_forward_rec(T(r), it))
+    assert torch.equal(res.mdc_adjoint_rec(T(u[idx]), it), st.mdc_adjoint_rec(T(u[idx]), it))
