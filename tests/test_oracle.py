@@ -367,6 +367,125 @@ def test_sgd_and_mask():
     np.testing.assert_allclose(optim.sgd(r, g, 0.5, on), [[[0.0, 0.0, -0.5, -1.0]]])
 
 
+# Nesterov momentum (Theory section: the N-SGD iteration, after Sutskever et al.).  The
+# pins below fix the look-ahead point, the order of the two updates and the masking,
+# each against something other than oracle.optim.nesterov itself.
+
+def test_nesterov_without_momentum_is_sgd():
+    """mu = 0: the velocity is -lr g(r) and the step is the SGD step, every step."""
+    r = rand((3, 2, 8), 60)
+    vel = np.zeros_like(r)
+    tgt = rand((3, 2, 8), 61)
+    on = np.array([[0, 3], [5, 1], [8, 2]], dtype=np.int32)
+    r = optim.apply_mask(r, on)
+    r_sgd = r.copy()
+    for _ in range(4):
+        r, vel = optim.nesterov(r, vel, lambda x: x - tgt, 0.3, 0.0, onset=on)
+        r_sgd = optim.sgd(r_sgd, r_sgd - tgt, 0.3, onset=on)
+        np.testing.assert_allclose(r, r_sgd, rtol=0, atol=1e-15)
+
+
+# f(x) = a x^2 / 2 with a = 2, lr = 0.1, mu = 0.5, x0 = 1, v0 = 0, unrolled by hand:
+#   v1 = -lr a x0 = -0.2,                    x1 = 0.8
+#   v2 = mu v1 - lr a (x1 + mu v1) = -0.24,  x2 = 0.56
+#   v3 = mu v2 - lr a (x2 + mu v2) = -0.208, x3 = 0.352
+_NESTEROV_1D = [(0.8, -0.2), (0.56, -0.24), (0.352, -0.208)]
+
+
+def _nesterov_1d(step):
+    x, v = np.array([1.0]), np.array([0.0])
+    out = []
+    for _ in range(3):
+        x, v = step(x, v)
+        out.append((float(x[0]), float(v[0])))
+    return out
+
+
+def test_nesterov_hand_unrolled_scalar_quadratic():
+    got = _nesterov_1d(lambda x, v: optim.nesterov(x, v, lambda y: 2.0 * y, 0.1, 0.5))
+    np.testing.assert_allclose(got, _NESTEROV_1D, rtol=0, atol=1e-15)
+
+
+def test_nesterov_three_term_recurrence_on_landweber_system():
+    """On the quadratic 1/2 ||A x - y||^2 of the Landweber example (Appendix B), each
+    eigen-direction of A^T A with eigenvalue lam follows the scalar three-term
+    recurrence e_{t+1} = (1 + mu)(1 - lr lam) e_t - mu (1 - lr lam) e_{t-1} (e = error
+    along that direction), with e_1 = (1 - lr lam) e_0 from v0 = 0.  The eigen-pairs
+    come from numpy's eigh, the recurrence is propagated per direction, and the iterates
+    must meet x = [1, 1]."""
+    gx = golden("landweber_example.json")
+    a = np.array(gx["A"], dtype=np.float64)
+    x_true = np.array(gx["x"], dtype=np.float64)
+    y = a @ x_true
+    lam, q = np.linalg.eigh(a.T @ a)
+    lr, mu = 1.0 / lam.max(), 0.9
+    x = np.zeros(2)
+    vel = np.zeros(2)
+    e_prev = q.T @ (x - x_true)
+    e_cur = (1.0 - lr * lam) * e_prev
+    for t in range(60):
+        x, vel = optim.nesterov(x, vel, lambda z: a.T @ (a @ z - y), lr, mu)
+        np.testing.assert_allclose(q.T @ (x - x_true), e_cur, rtol=0, atol=1e-12)
+        e_prev, e_cur = e_cur, (1 + mu) * (1 - lr * lam) * e_cur - mu * (1 - lr * lam) * e_prev
+    for _ in range(400):
+        x, vel = optim.nesterov(x, vel, lambda z: a.T @ (a @ z - y), lr, mu)
+    np.testing.assert_allclose(x, x_true, atol=1e-10)
+
+
+def test_nesterov_look_ahead_reparametrisation():
+    """In the look-ahead variable phi = r + mu vel the same iteration reads
+    phi <- phi + mu^2 vel - (1 + mu) lr g(phi), vel <- mu vel - lr g(phi): the gradient is
+    evaluated at phi, the point the next step starts from."""
+    c = rand((4, 6), 62)
+    h = c.T @ c + 0.1 * np.eye(6)
+    b = rand(6, 63)
+
+    def grad(z):
+        return h @ z - b
+
+    lr, mu = 0.05, 0.8
+    r = rand(6, 64)
+    vel = rand(6, 65)
+    phi = r + mu * vel
+    vphi = vel.copy()
+    for _ in range(10):
+        r, vel = optim.nesterov(r, vel, grad, lr, mu)
+        g = grad(phi)
+        phi = phi + mu * mu * vphi - (1 + mu) * lr * g
+        vphi = mu * vphi - lr * g
+        np.testing.assert_allclose(r + mu * vel, phi, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(vel, vphi, rtol=0, atol=1e-12)
+
+
+def test_nesterov_keeps_muted_samples_zero():
+    """Causality preconditioner: model and velocity stay zero before each trace's onset,
+    even with a gradient that is nonzero there."""
+    on = np.array([[2, 0], [7, 4]], dtype=np.int32)
+    r = optim.apply_mask(rand((2, 2, 8), 66), on)
+    vel = np.zeros_like(r)
+    keep = optim.causal_mask(on, 8)
+    for _ in range(5):
+        r, vel = optim.nesterov(r, vel, lambda z: z + 1.0, 0.2, 0.9, onset=on)
+        assert np.all(r[keep == 0] == 0.0) and np.all(vel[keep == 0] == 0.0)
+        assert np.all(r[keep == 1] != 0.0)
+
+
+def test_nesterov_pins_catch_planted_look_ahead_mistake():
+    """The gradient taken at r instead of r + mu vel (heavy-ball momentum) must fail the
+    hand-unrolled pin; so must the velocity update applied after the model update."""
+    def heavy_ball(x, v):
+        v = 0.5 * v - 0.1 * 2.0 * x
+        return x + v, v
+
+    def late_velocity(x, v):
+        x = x + v
+        return x, 0.5 * v - 0.1 * 2.0 * (x + 0.5 * v)
+
+    for wrong in (heavy_ball, late_velocity):
+        got = _nesterov_1d(wrong)
+        assert np.abs(np.array(got) - np.array(_NESTEROV_1D)).max() > 1e-3
+
+
 def test_rmse_properties():
     a = rand((3, 4, 5), 37)
     assert optim.rmse(a, a) == 0.0
