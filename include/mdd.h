@@ -154,8 +154,11 @@ mdd_status mdd_set_mask(mdd_plan* plan, const int32_t* onset);
 mdd_status mdc_forward(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
                        float* U_out);
 
-/* Adjoint MDC on a batch: G_out = sum_b P+_{idx[b]}^H V[b], G_out [nr][nvs][nt]
- * float32, V [nb][nvs][nt].  No mask is applied.  Needs mdd_set_kernel. */
+/* Adjoint MDC on a batch (Theory section: the adjoint P+^H that the mini-batch
+ * gradient, Eq. (6), applies to the residual; per frequency the product with the
+ * conjugate transpose of the kernel rows, Appendix A): G_out = sum_b
+ * P+_{idx[b]}^H V[b], G_out [nr][nvs][nt] float32, V [nb][nvs][nt].  No mask is
+ * applied.  Needs mdd_set_kernel. */
 mdd_status mdc_adjoint(mdd_plan* plan, const float* V, const int32_t* idx, int32_t nb,
                        float* G_out);
 
@@ -202,7 +205,9 @@ mdd_status mdd_stage_kernel(mdd_plan* plan, const float* d_rows, int32_t nb);
  * [1, nb_max]).  Calls no HIP function. */
 mdd_status mdd_check_batch_host(const int32_t* idx_host, int32_t nb, int32_t ns, int32_t nb_max);
 
-/* One stochastic step in place: the gradient of mdd_stoch_grad at R (or, for
+/* One stochastic step in place (Theory section: the SGD iteration r <- r - alpha g
+ * on the batch gradient of Eq. (6), and its Nesterov-momentum form N-SGD; Adam is
+ * not in the paper): the gradient of mdd_stoch_grad at R (or, for
  * MDD_OPT_NSGD, at R + mu s0), then the update of R and of the optimiser state
  * s0, s1 ([nr][nvs][nt] float32 each): SGD uses neither (may be NULL), NSGD
  * uses s0 (velocity), ADAM uses s0 (first moment) and s1 (second moment).
@@ -263,6 +268,21 @@ mdd_status mdd_sigma_max2(mdd_plan* plan, int32_t iters, double* lam_out);
 #define MDD_KC_COUNT 6
 mdd_status mdd_profile_enable(mdd_plan* plan, int32_t enable, int32_t capacity);
 mdd_status mdd_profile_read(mdd_plan* plan, double* ms_host, int64_t* count_host);
+
+/* Measurement aid, not a step of the method: moves the HBM bytes of one Adam update
+ * launch (R, s0, s1 [rows][ncols][nt] float32 read and written in place, and the
+ * spectra spec [rows][ceil(ncols/16)][nf][16] complex float32 read and written in
+ * place) without its transforms, so that its duration is the floor the memory
+ * system sets for the update kernel at these sizes.  variant 0: the update kernel's
+ * grid, workgroup mapping, spectra staging and 8-byte per-lane accesses; 1: the same
+ * with 16-byte per-lane accesses; 2: flat streams over the three arrays and the
+ * spectra (two launches).  The arrays' contents are overwritten with meaningless
+ * values.  Pointers 16-byte aligned; enqueued on `stream`.  Errors: EINVAL (NULL,
+ * misaligned, variant), ESHAPE (rows or ncols outside [1, 4096], nt not one of
+ * 128, 256, 512, 1024, nf outside [1, nt/2 + 1]), EHIP. */
+mdd_status mdd_calibrate_update(float* R, float* s0, float* s1, float* spec, int32_t rows,
+                                int32_t ncols, int32_t nt, int32_t nf, int32_t variant,
+                                void* stream);
 
 /* Static description of a status code. */
 const char* mdd_status_string(mdd_status status);

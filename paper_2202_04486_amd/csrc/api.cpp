@@ -626,6 +626,23 @@ mdd_status mdd_reciprocity(const float* z, float* out, int32_t n, int32_t nt, vo
              : MDD_EHIP;
 }
 
+mdd_status mdd_calibrate_update(float* R, float* s0, float* s1, float* spec, int32_t rows,
+                                int32_t ncols, int32_t nt, int32_t nf, int32_t variant,
+                                void* stream) {
+  if (!R || !s0 || !s1 || !spec) return MDD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(R) | reinterpret_cast<uintptr_t>(s0) |
+       reinterpret_cast<uintptr_t>(s1) | reinterpret_cast<uintptr_t>(spec)) & 15)
+    return MDD_EINVAL;
+  if (variant < 0 || variant > 2) return MDD_EINVAL;
+  if (rows < 1 || rows > MAX_EXTENT || ncols < 1 || ncols > MAX_EXTENT || !valid_nt(nt))
+    return MDD_ESHAPE;
+  if (nf < 1 || nf > nt / 2 + 1) return MDD_ESHAPE;
+  return launch_calibrate_update(R, s0, s1, reinterpret_cast<float2*>(spec), rows, ncols, nt, nf,
+                                 variant, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? MDD_OK
+             : MDD_EHIP;
+}
+
 mdd_status mdd_check_batch_host(const int32_t* idx_host, int32_t nb, int32_t ns, int32_t nb_max) {
   if (!idx_host) return MDD_EINVAL;
   if (nb < 1 || nb > nb_max) return MDD_ESHAPE;

@@ -118,6 +118,10 @@ hipError_t launch_freq_absmax(const float2* Df, int nf, long long count, long lo
 hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int iters,
                         double* lam_out, hipStream_t s);
 
+// Measurement aid (calibrate.hip): the update kernel's HBM traffic without its transforms.
+hipError_t launch_calibrate_update(float* R, float* M, float* V, float2* spec, int rows,
+                                   int ncols, int nt, int nf, int variant, hipStream_t s);
+
 // Blocks of ncols columns.
 inline int nblocks(int ncols) { return (ncols + CB - 1) / CB; }
 inline int round16(int n) { return nblocks(n) * CB; }

@@ -26,8 +26,8 @@ EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_pl
            "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
            "mdd_sigma_max2",
-           "mdd_profile_enable", "mdd_profile_read", "mdd_status_string",
-           "mdd_plan_last_hip_error")
+           "mdd_profile_enable", "mdd_profile_read", "mdd_calibrate_update",
+           "mdd_status_string", "mdd_plan_last_hip_error")
 
 
 class Dims(ctypes.Structure):
@@ -87,6 +87,7 @@ def load() -> ctypes.CDLL:
         "mdd_profile_enable": (_I32, [_P, _I32, _I32]),
         "mdd_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]),
+        "mdd_calibrate_update": (_I32, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P]),
         "mdd_status_string": (ctypes.c_char_p, [_I32]),
         "mdd_plan_last_hip_error": (_I32, [_P]),
     }

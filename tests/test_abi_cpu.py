@@ -158,3 +158,15 @@ def test_reciprocity_rejects_bad_arguments_on_the_host(lib):
     assert lib.mdd_reciprocity(ctypes.c_void_p(4100), p, 4, 128, None) == native.MDD_EINVAL
     assert lib.mdd_reciprocity(p, p, 0, 128, None) == native.MDD_ESHAPE
     assert lib.mdd_reciprocity(p, p, 4, 100, None) == native.MDD_ESHAPE
+
+
+def test_calibration_rejects_bad_arguments_on_the_host(lib):
+    p = ctypes.c_void_p(4096)
+    E, S = native.MDD_EINVAL, native.MDD_ESHAPE
+    assert lib.mdd_calibrate_update(None, p, p, p, 4, 20, 512, 200, 0, None) == E
+    assert lib.mdd_calibrate_update(p, p, p, ctypes.c_void_p(4104), 4, 20, 512, 200, 0, None) == E
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 200, 3, None) == E
+    assert lib.mdd_calibrate_update(p, p, p, p, 0, 20, 512, 200, 0, None) == S
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 5000, 512, 200, 0, None) == S
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 500, 200, 0, None) == S
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 258, 0, None) == S

@@ -43,3 +43,57 @@ def test_committed_summaries_match_the_current_kernels():
                            ("diff301", ("products", "reciprocity", "spec_reciprocity"))):
         for k in keys:
             assert bench.stored_traffic(workload, k) is not None, (workload, k)
+
+
+def _tiny_problem(nvs=12):
+    import numpy as np
+    import torch
+
+    import synth
+    wl = synth.WORKLOADS["tiny2d"].replace(ns=10, nr=9, nvs=nvs, nt=64, nf=20, nb=4)
+    rng = np.random.default_rng(3)
+    d = torch.from_numpy(rng.standard_normal((wl.ns, wl.nr, wl.nt)))
+    u = torch.from_numpy(rng.standard_normal((wl.ns, wl.nvs, wl.nt)))
+    onset = rng.integers(0, 8, size=(wl.nr, wl.nvs)).astype(np.int32)
+    return wl, d, u, onset
+
+
+def test_oracle_on_columns_equals_the_full_gradient_columns():
+    """The bench checks the GPU gradient on a few virtual-source columns: without
+    reciprocity those columns of the oracle's gradient do not depend on the others,
+    also when several models' columns share one oracle call."""
+    import numpy as np
+    import torch
+
+    import bench
+    from oracle import freq, optim
+    wl, d, u, onset = _tiny_problem()
+    R = torch.from_numpy(np.random.default_rng(4).standard_normal((wl.nr, wl.nvs, wl.nt)))
+    idx = np.array([1, 4, 7, 8])
+    _, g = freq.batch_loss_grad(d.numpy(), R.numpy(), u.numpy(), idx, wl.nf)
+    g = optim.apply_mask(g, onset)
+    cols = np.array([0, 5, 11])
+    gc = bench.oracle_gradient_columns(wl, d, u, onset, R[:, cols].numpy(), idx, cols)
+    np.testing.assert_allclose(gc, g[:, cols], rtol=0, atol=1e-12 * np.abs(g).max())
+    two = np.concatenate([R[:, cols].numpy(), 2 * R[:, cols].numpy()], axis=1)
+    gg = bench.oracle_gradient_columns(wl, d, u, onset, two, idx, cols, reps=2)
+    np.testing.assert_allclose(gg[:, :3], g[:, cols], rtol=0, atol=1e-12 * np.abs(g).max())
+    errs = bench.gradient_errors(wl, d, u, onset, R, {"same": torch.from_numpy(g)}, idx, cols)
+    assert errs["same"] < 1e-14
+
+
+def test_cpu_baseline_on_columns_extrapolates_linearly():
+    import bench
+    wl, d, u, onset = _tiny_problem(nvs=40)
+    cb = bench.cpu_baseline_columns(wl, d, u, onset, budget_s=30.0, ks=(4, 16), steps_per_k=1)
+    t = {int(k): v for k, v in cb["seconds_per_step_measured"].items()}
+    assert set(t) == {4, 16} and cb["value"] > 0 and cb["kind"] == "oracle"
+    slope = (t[16] - t[4]) / 12
+    assert abs(cb["seconds_per_full_step"] - (max(t[4] - 4 * slope, 0) + 40 * slope)) < 1e-12
+    assert "columns" in cb["sample"] and cb["cores"] >= 1
+
+
+def test_host_cpu_names_the_model():
+    import bench
+    model, n = bench.host_cpu()
+    assert isinstance(model, str) and n >= 1
