@@ -62,6 +62,7 @@ typedef int32_t mdd_status;
 #define MDD_EHIP (-4)         /* a HIP runtime call failed */
 #define MDD_EUNSUPPORTED (-5) /* precision or optimiser not available */
 #define MDD_ESTATE (-6)       /* kernel / data not set before a call that needs them */
+#define MDD_ELIMIT (-7)       /* sizes beyond the library's static workspace (the _noalloc call) */
 
 /* Arithmetic of the two per-frequency complex products.  With one virtual source
  * (nvs = 1) the products are matrix-vector products bound by the bytes of D_b and
@@ -184,6 +185,27 @@ mdd_status mdc_adjoint_rec(mdd_plan* plan, const float* V, const int32_t* idx, i
  * float64 scalars (either may be NULL).  Needs kernel and data. */
 mdd_status mdd_stoch_grad(mdd_plan* plan, const float* R, const int32_t* idx, int32_t nb,
                           float* G_out, double* loss_out, double* gnorm2_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the mini-batch gradient of
+ * mdd_stoch_grad, with the plan's set-up (mdd_set_kernel, mdd_set_data,
+ * mdd_set_mask) done in the same call, on a plan laid out in a workspace the library
+ * itself holds: one static device array of MDD_NOALLOC_WORKSPACE_BYTES per GPU,
+ * resident from the library's first use on that GPU until the process ends.  No
+ * device or host memory is allocated.  dims as for mdd_plan_create (flags
+ * MDD_FLAG_STREAM_KERNEL and MDD_FLAG_FULL_GRAD are rejected); d, u, onset (may be
+ * NULL), R, idx, nb, G_out, loss_out, gnorm2_out as for mdd_set_kernel,
+ * mdd_set_data, mdd_set_mask and mdd_stoch_grad.  `stream` must belong to the
+ * current device.  Every call on one GPU uses that GPU's array: calls that overlap
+ * in time on one GPU (other streams, other threads) race and must be serialised by
+ * the caller; a call's results do not depend on what an earlier call left there.
+ * Errors: EINVAL (NULL, flags, a stream of another device), ESHAPE, EUNSUPPORTED,
+ * ELIMIT (mdd_workspace_bytes(dims) above MDD_NOALLOC_WORKSPACE_BYTES), EHIP. */
+#define MDD_NOALLOC_WORKSPACE_BYTES (64u << 20)
+mdd_status mdd_stoch_grad_noalloc(const mdd_dims* dims, const float* d, const float* u,
+                                  const int32_t* onset, const float* R, const int32_t* idx,
+                                  int32_t nb, float* G_out, double* loss_out, double* gnorm2_out,
+                                  void* stream);
 
 /* Kernel rows of one batch, for a plan with MDD_FLAG_STREAM_KERNEL (Examples and
  * Appendix A: with 3D acquisitions the kernel may not fit in memory; a step only

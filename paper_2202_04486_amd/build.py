@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmdd.so")
 SOURCES = ["api.cpp", "trace_kernels.hip", "gemm_kernels.hip", "gemm_split.hip",
-           "gemv_kernels.hip", "reduce_kernels.hip", "calibrate.hip"]
+           "gemv_kernels.hip", "reduce_kernels.hip", "calibrate.hip",
+           "noalloc.hip"]
 ARCH = os.environ.get("MDD_OFFLOAD_ARCH", "gfx950")
 
 

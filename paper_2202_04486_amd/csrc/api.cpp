@@ -324,6 +324,26 @@ size_t mdd_workspace_bytes(const mdd_dims* dims) {
   return make_layout(*dims).total;
 }
 
+}  // extern "C"
+
+// Lays a plan out in a workspace of at least make_layout(*dims).total bytes and
+// enqueues its tables (dims already checked).
+static hipError_t init_plan(mdd_plan* p, const mdd_dims* dims, const Layout& L, void* workspace,
+                            void* stream) {
+  p->d = *dims;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->ws = reinterpret_cast<char*>(workspace);
+  p->L = L;
+  p->nrp = round16(dims->nr);
+  p->nvsp = round16(dims->nvs);
+  p->nvb = nblocks(dims->nvs);
+  hipError_t e = launch_twiddles(p->tw(), dims->nt, p->stream);
+  if (e == hipSuccess && p->full()) e = launch_iota(p->sidx(), dims->ns, p->stream);
+  return e;
+}
+
+extern "C" {
+
 mdd_status mdd_plan_create(const mdd_dims* dims, void* workspace, size_t ws_bytes, void* stream,
                            mdd_plan** out) {
   if (!out) return MDD_EINVAL;
@@ -334,16 +354,7 @@ mdd_status mdd_plan_create(const mdd_dims* dims, void* workspace, size_t ws_byte
     return MDD_ENOMEM;
   mdd_plan* p = new (std::nothrow) mdd_plan();
   if (!p) return MDD_ENOMEM;
-  p->d = *dims;
-  p->stream = reinterpret_cast<hipStream_t>(stream);
-  p->ws = reinterpret_cast<char*>(workspace);
-  p->L = L;
-  p->nrp = round16(dims->nr);
-  p->nvsp = round16(dims->nvs);
-  p->nvb = nblocks(dims->nvs);
-  hipError_t e = launch_twiddles(p->tw(), dims->nt, p->stream);
-  if (e == hipSuccess && p->full()) e = launch_iota(p->sidx(), dims->ns, p->stream);
-  if (e != hipSuccess) {
+  if (init_plan(p, dims, L, workspace, stream) != hipSuccess) {
     delete p;
     return MDD_EHIP;
   }
@@ -569,6 +580,34 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
   return p->reduce(idx, nb, true, loss_out, gnorm2_out);
 }
 
+mdd_status mdd_stoch_grad_noalloc(const mdd_dims* dims, const float* d, const float* u,
+                                  const int32_t* onset, const float* R, const int32_t* idx,
+                                  int32_t nb, float* G_out, double* loss_out, double* gnorm2_out,
+                                  void* stream) {
+  if (!dims || !d || !u || !R || !idx || !G_out) return MDD_EINVAL;
+  MDD_TRY(check_dims(dims));
+  if (dims->flags & (MDD_FLAG_STREAM_KERNEL | MDD_FLAG_FULL_GRAD)) return MDD_EINVAL;
+  if (nb < 1 || nb > dims->nb_max) return MDD_ESHAPE;
+  const Layout L = make_layout(*dims);
+  if (L.total > static_workspace_bytes()) return MDD_ELIMIT;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MDD_EHIP;
+  if (s) {  // the stream must belong to the current device, whose workspace is used
+    int sdev = -1;
+    if (hipStreamGetDevice(s, &sdev) != hipSuccess) return MDD_EHIP;
+    if (sdev != dev) return MDD_EINVAL;
+  }
+  void* ws = nullptr;
+  if (static_workspace(dev, &ws) != hipSuccess) return MDD_EHIP;
+  mdd_plan p;  // host object on the stack; its event lists stay empty
+  if (init_plan(&p, dims, L, ws, stream) != hipSuccess) return MDD_EHIP;
+  MDD_TRY(mdd_set_kernel(&p, d));
+  MDD_TRY(mdd_set_data(&p, u));
+  MDD_TRY(mdd_set_mask(&p, onset));
+  return mdd_stoch_grad(&p, R, idx, nb, G_out, loss_out, gnorm2_out);
+}
+
 mdd_status mdd_full_grad(mdd_plan* p, const float* R, float* G_out, double* loss_out,
                          double* gnorm2_out) {
   if (!p || !R || !G_out) return MDD_EINVAL;
@@ -719,6 +758,7 @@ const char* mdd_status_string(mdd_status s) {
     case MDD_EHIP: return "HIP runtime error";
     case MDD_EUNSUPPORTED: return "unsupported precision or optimiser";
     case MDD_ESTATE: return "kernel or data not set";
+    case MDD_ELIMIT: return "sizes need more than the library's static workspace";
     default: return "unknown status";
   }
 }

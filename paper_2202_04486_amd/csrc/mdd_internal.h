@@ -122,6 +122,11 @@ hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int i
 hipError_t launch_calibrate_update(float* R, float* M, float* V, float2* spec, int rows,
                                    int ncols, int nt, int nf, int variant, hipStream_t s);
 
+// The library's static workspace (noalloc.hip): its size, and its address on `device`,
+// which must be the current device (looked up once per device, then cached).
+size_t static_workspace_bytes();
+hipError_t static_workspace(int device, void** out);
+
 // Blocks of ncols columns.
 inline int nblocks(int ncols) { return (ncols + CB - 1) / CB; }
 inline int round16(int n) { return nblocks(n) * CB; }

@@ -12,6 +12,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libm
 
 MDD_OK, MDD_EINVAL, MDD_ESHAPE, MDD_ENOMEM, MDD_EHIP, MDD_EUNSUPPORTED, MDD_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
+MDD_ELIMIT = -7
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3, "fp32_cgemm": 4}
 FLAG_STORE_RF = 1
 FLAG_FULL_GRAD = 2
@@ -23,7 +25,7 @@ KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft", "reciprocity")
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
            "mdd_set_kernel", "mdd_stage_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward",
            "mdc_adjoint", "mdc_forward_rec", "mdc_adjoint_rec",
-           "mdd_stoch_grad", "mdd_step", "mdd_full_grad", "mdd_full_step",
+           "mdd_stoch_grad", "mdd_stoch_grad_noalloc", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
            "mdd_sigma_max2",
            "mdd_profile_enable", "mdd_profile_read", "mdd_calibrate_update",
@@ -77,6 +79,8 @@ def load() -> ctypes.CDLL:
         "mdc_forward_rec": (_I32, [_P, _P, _P, _I32, _P]),
         "mdc_adjoint_rec": (_I32, [_P, _P, _P, _I32, _P]),
         "mdd_stoch_grad": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
+        "mdd_stoch_grad_noalloc": (_I32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _I32, _P, _P,
+                                          _P, _P]),
         "mdd_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _I32, _P, _P]),
         "mdd_full_grad": (_I32, [_P, _P, _P, _P, _P]),
         "mdd_full_step": (_I32, [_P, _P, _P, _P, ctypes.POINTER(Opt), _P, _P]),

@@ -126,7 +126,7 @@ def test_null_plan_rejected_everywhere(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = native.status_string(code)
         assert isinstance(s, str) and s
     assert native.status_string(-99) == "unknown status"
@@ -170,3 +170,26 @@ def test_calibration_rejects_bad_arguments_on_the_host(lib):
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 5000, 512, 200, 0, None) == S
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 500, 200, 0, None) == S
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 258, 0, None) == S
+
+
+def test_noalloc_gradient_rejects_on_the_host(lib):
+    """mdd_stoch_grad_noalloc checks its arguments and the size of the plan against the
+    static workspace before any HIP call."""
+    p = ctypes.c_void_p(4096)
+    d = dims()
+    assert native.workspace_bytes(d) <= native.NOALLOC_WORKSPACE_BYTES
+    E = native.MDD_EINVAL
+    assert lib.mdd_stoch_grad_noalloc(None, p, p, None, p, p, 4, p, None, None, None) == E
+    assert lib.mdd_stoch_grad_noalloc(ctypes.byref(d), None, p, None, p, p, 4, p, None, None, None) == E
+    assert lib.mdd_stoch_grad_noalloc(ctypes.byref(d), p, p, None, p, p, 4, None, None, None, None) == E
+    assert lib.mdd_stoch_grad_noalloc(ctypes.byref(d), p, p, None, p, p, 9, p, None, None,
+                                      None) == native.MDD_ESHAPE
+    for flag in (native.FLAG_STREAM_KERNEL, native.FLAG_FULL_GRAD):
+        df = dims(flags=flag)
+        assert lib.mdd_stoch_grad_noalloc(ctypes.byref(df), p, p, None, p, p, 4, p, None, None,
+                                          None) == E
+    big = dims(ns=1024, nr=1024, nvs=64, nt=512, nf=200, nb_max=8)
+    assert native.workspace_bytes(big) > native.NOALLOC_WORKSPACE_BYTES
+    assert lib.mdd_stoch_grad_noalloc(ctypes.byref(big), p, p, None, p, p, 4, p, None, None,
+                                      None) == native.MDD_ELIMIT
+    assert "static workspace" in native.status_string(native.MDD_ELIMIT)
