@@ -84,11 +84,17 @@ typedef int32_t mdd_status;
                                 for mdd_full_grad / mdd_full_step */
 #define MDD_FLAG_STREAM_KERNEL 4 /* keep no kernel spectra for all sources: the caller stages
                                     each batch's rows with mdd_stage_kernel (the kernel may
-                                    then live out of device memory); not with FULL_GRAD */
+                                    then live out of device memory); not with FULL_GRAD.
+                                    Lifts the 4096 limit on ns to 1048576 */
+#define MDD_FLAG_STREAM_DATA 8   /* with MDD_FLAG_STREAM_KERNEL: keep no data spectra for all
+                                    sources either; the caller stages each batch's data rows
+                                    with mdd_stage_data.  The workspace then does not grow
+                                    with ns */
 
-/* Sizes.  ns sources, nr receivers, nvs virtual sources, nt time samples
- * (128, 256, 512 or 1024), nf retained one-sided frequency bins (1..nt/2+1),
- * nb_max the largest batch any call on this plan will use (1..ns, <= 64). */
+/* Sizes.  ns sources (at most 4096, or 1048576 with MDD_FLAG_STREAM_KERNEL), nr
+ * receivers and nvs virtual sources (at most 4096), nt time samples (128, 256, 512
+ * or 1024), nf retained one-sided frequency bins (1..nt/2+1), nb_max the largest
+ * batch any call on this plan will use (1..ns, <= 64). */
 typedef struct mdd_dims {
   int32_t ns, nr, nvs, nt, nf, nb_max;
   int32_t precision; /* MDD_PREC_* */
@@ -219,6 +225,17 @@ mdd_status mdd_stoch_grad_noalloc(const mdd_dims* dims, const float* d, const fl
  * Errors: EINVAL (NULL), ESTATE (plan without the flag), ESHAPE (nb outside
  * [1, nb_max]), EHIP. */
 mdd_status mdd_stage_kernel(mdd_plan* plan, const float* d_rows, int32_t nb);
+
+/* Data rows of one batch, for a plan with MDD_FLAG_STREAM_DATA (the same concern
+ * as mdd_stage_kernel: with 10^3 - 10^5 sources the up-going data need not stay in
+ * device memory either).  u_rows [nb][nvs][nt] float32 device: row b is the up-going
+ * wavefield of the source the next call's idx[b] names.  Computes their spectra and
+ * out-of-band energies in place of mdd_set_data's; the following mdd_stoch_grad /
+ * mdd_step must pass a batch of the same length nb and take U row b and its energy
+ * from here (an index outside [0, ns) still acts as a zero source).  mdd_set_data
+ * returns ESTATE on such a plan.  Errors: EINVAL (NULL), ESTATE (plan without the
+ * flag), ESHAPE (nb outside [1, nb_max]), EHIP. */
+mdd_status mdd_stage_data(mdd_plan* plan, const float* u_rows, int32_t nb);
 
 /* Host-side check of a batch before it is enqueued: idx_host [nb] in host memory.
  * The device entry points treat an index outside [0, ns) as a source with zero

@@ -14,6 +14,9 @@ using namespace mdd;
 namespace {
 
 constexpr int MAX_EXTENT = 4096;  // ns, nr, nvs: the power iteration keeps vectors in LDS
+// ns of a plan with MDD_FLAG_STREAM_KERNEL: such a plan runs no power iteration and
+// keeps no per-source kernel spectra (and, with MDD_FLAG_STREAM_DATA, no per-source data).
+constexpr int MAX_STREAM_NS = 1 << 20;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -37,9 +40,12 @@ Layout make_layout(const mdd_dims& d) {
   // kernel spectra: every source, or (MDD_FLAG_STREAM_KERNEL) the staged batch rows
   const size_t drows = (d.flags & MDD_FLAG_STREAM_KERNEL) ? d.nb_max : d.ns;
   L.df = take(c8 * d.nf * drows * nrp);
-  L.uf = take(c8 * d.nf * d.ns * nvsp);
-  L.oob = take(sizeof(double) * d.ns);
-  L.oobp = take(sizeof(double) * d.ns * nvb);
+  // data spectra and out-of-band energies: every source, or (MDD_FLAG_STREAM_DATA) the
+  // staged batch rows
+  const size_t urows = (d.flags & MDD_FLAG_STREAM_DATA) ? d.nb_max : d.ns;
+  L.uf = take(c8 * d.nf * urows * nvsp);
+  L.oob = take(sizeof(double) * urows);
+  L.oobp = take(sizeof(double) * urows * nvb);
   L.onset = take(sizeof(int32_t) * d.nr * d.nvs);
   L.f = take(c8 * d.nr * nvb * d.nf * CB);
   L.bsp = take(c8 * d.nb_max * nvb * d.nf * CB);
@@ -62,12 +68,17 @@ Layout make_layout(const mdd_dims& d) {
 mdd_status check_dims(const mdd_dims* d) {
   if (!d) return MDD_EINVAL;
   if (d->ns < 1 || d->nr < 1 || d->nvs < 1 || d->nb_max < 1 || d->nf < 1) return MDD_ESHAPE;
-  if (d->ns > MAX_EXTENT || d->nr > MAX_EXTENT || d->nvs > MAX_EXTENT) return MDD_ESHAPE;
+  const int ns_max = (d->flags & MDD_FLAG_STREAM_KERNEL) ? MAX_STREAM_NS : MAX_EXTENT;
+  if (d->ns > ns_max || d->nr > MAX_EXTENT || d->nvs > MAX_EXTENT) return MDD_ESHAPE;
   if (!valid_nt(d->nt)) return MDD_ESHAPE;
   if (d->nf > d->nt / 2 + 1) return MDD_ESHAPE;
   if (d->nb_max > d->ns || d->nb_max > NB_LIMIT) return MDD_ESHAPE;
   if (d->precision < MDD_PREC_FP32 || d->precision > MDD_PREC_FP32_CGEMM) return MDD_EUNSUPPORTED;
-  if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD | MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
+  if (d->flags & ~(MDD_FLAG_STORE_RF | MDD_FLAG_FULL_GRAD | MDD_FLAG_STREAM_KERNEL |
+                   MDD_FLAG_STREAM_DATA))
+    return MDD_EINVAL;
+  // staged data rows come with staged kernel rows
+  if ((d->flags & MDD_FLAG_STREAM_DATA) && !(d->flags & MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
   // the full gradient visits every source: it needs the resident kernel spectra
   if ((d->flags & MDD_FLAG_FULL_GRAD) && (d->flags & MDD_FLAG_STREAM_KERNEL)) return MDD_EINVAL;
   return MDD_OK;
@@ -123,12 +134,21 @@ struct mdd_plan {
   // MDD_FLAG_STREAM_KERNEL: Df holds the rows of the last staged batch (staged_nb rows).
   bool streamed() const { return (d.flags & MDD_FLAG_STREAM_KERNEL) != 0; }
   int staged_nb = 0;
-  // A call on a batch of nb entries: with staged kernel rows, the batch must be the
-  // staged one (same length; entry b uses staged row b).
+  // MDD_FLAG_STREAM_DATA: Uf and oob hold the rows of the last staged batch.
+  bool streamed_data() const { return (d.flags & MDD_FLAG_STREAM_DATA) != 0; }
+  int staged_u_nb = 0;
+  // A call on a batch of nb entries: with staged kernel (and data) rows, the batch must
+  // be the staged one (same length; entry b uses staged row b).
   mdd_status batch_ok(int nb) const {
     if (nb < 1 || nb > d.nb_max) return MDD_ESHAPE;
     if (streamed() && staged_nb == 0) return MDD_ESTATE;
     if (streamed() && nb != staged_nb) return MDD_ESHAPE;
+    return MDD_OK;
+  }
+  // The same for the operators that read the data rows (gradient, step).
+  mdd_status data_batch_ok(int nb) const {
+    if (streamed_data() && staged_u_nb == 0) return MDD_ESTATE;
+    if (streamed_data() && nb != staged_u_nb) return MDD_ESHAPE;
     return MDD_OK;
   }
   // One virtual source: the time arrays [rows][1][nt] are handled as one row of `rows`
@@ -198,6 +218,8 @@ struct mdd_plan {
     g.nb = nb;
     g.dns = streamed() ? d.nb_max : d.ns;
     g.dpos = streamed() ? 1 : 0;
+    g.uns = streamed_data() ? d.nb_max : d.ns;
+    g.upos = streamed_data() ? 1 : 0;
     if (vs1()) {
       g.P = gemv_groups(nb, d.nf);
       g.gpart = gvp();
@@ -231,6 +253,7 @@ struct mdd_plan {
     r.idx = idx;
     r.nb = nb;
     r.ns = d.ns;
+    r.oob_pos = streamed_data() ? 1 : 0;
     r.gn_part = gnp();
     r.n_gn = gnorm2_out ? n_gn() : 0;
     r.loss_out = loss_out;
@@ -427,25 +450,42 @@ mdd_status mdd_stage_kernel(mdd_plan* p, const float* d_rows, int32_t nb) {
   return MDD_OK;
 }
 
-mdd_status mdd_set_data(mdd_plan* p, const float* u) {
-  if (!p || !u) return MDD_EINVAL;
+// Data spectra and out-of-band energies of `rows` sources u [rows][nvs][nt], into data
+// spectra with `urows` rows per frequency.
+static mdd_status data_spectra(mdd_plan* p, const float* u, int rows, int urows) {
   TraceArgs a{};
   a.nt = p->d.nt;
   a.nf = p->d.nf;
-  a.rows = p->d.ns;
+  a.rows = rows;
   a.ncols = p->d.nvs;
   a.ncb = p->nvb;
   a.x_in = u;
   a.spec = p->Uf();
   a.s_row = p->nvsp;
   a.s_cb = CB;
-  a.s_k = (long long)p->d.ns * p->nvsp;
+  a.s_k = (long long)urows * p->nvsp;
   a.part = p->oobp();
   a.tw = p->tw();
   MDD_TRY(p->run(MDD_KC_DATA_FFT, [&] { return launch_trace(TM_RFFT, a, p->stream); }));
-  MDD_TRY(p->run(MDD_KC_REDUCE, [&] {
-    return launch_row_sum(p->oobp(), p->d.ns, p->nvb, 1.0 / (2.0 * p->d.nt), p->oob(), p->stream);
-  }));
+  return p->run(MDD_KC_REDUCE, [&] {
+    return launch_row_sum(p->oobp(), rows, p->nvb, 1.0 / (2.0 * p->d.nt), p->oob(), p->stream);
+  });
+}
+
+mdd_status mdd_stage_data(mdd_plan* p, const float* u_rows, int32_t nb) {
+  if (!p || !u_rows) return MDD_EINVAL;
+  if (!p->streamed_data()) return MDD_ESTATE;
+  if (nb < 1 || nb > p->d.nb_max) return MDD_ESHAPE;
+  MDD_TRY(data_spectra(p, u_rows, nb, p->d.nb_max));
+  p->staged_u_nb = nb;
+  p->data_set = true;
+  return MDD_OK;
+}
+
+mdd_status mdd_set_data(mdd_plan* p, const float* u) {
+  if (!p || !u) return MDD_EINVAL;
+  if (p->streamed_data()) return MDD_ESTATE;  // such a plan takes batch rows (mdd_stage_data)
+  MDD_TRY(data_spectra(p, u, p->d.ns, p->d.ns));
   p->data_set = true;
   return MDD_OK;
 }
@@ -539,6 +579,7 @@ mdd_status mdd_stoch_grad(mdd_plan* p, const float* R, const int32_t* idx, int32
   if (!p || !R || !idx || !G_out) return MDD_EINVAL;
   MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
+  MDD_TRY(p->data_batch_ok(nb));
   p->spec_model = nullptr;
   MDD_TRY(p->model_fft(R, nullptr, 0.0));
   const GemmArgs g = p->gemm(idx, nb);
@@ -556,6 +597,7 @@ mdd_status mdd_step(mdd_plan* p, float* R, float* s0, float* s1, const mdd_opt* 
   if (!p || !R || !opt || !idx) return MDD_EINVAL;
   MDD_TRY(p->batch_ok(nb));
   if (!p->kernel_set || !p->data_set) return MDD_ESTATE;
+  MDD_TRY(p->data_batch_ok(nb));
   TraceArgs a = p->blocked(p->F(), p->d.nr);
   int mode = 0;
   MDD_TRY(update_args(*opt, s0, s1, a, mode));

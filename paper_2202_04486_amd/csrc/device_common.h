@@ -46,6 +46,13 @@ __device__ __forceinline__ int drow_of(const GemmArgsT& a, int b, int s) {
   return a.dpos ? b : s;
 }
 
+// Offset of row (k, .) of U_k for batch entry b with source s: row s of the resident
+// data spectra, or row b of data spectra staged for the batch.  Callers pass b < nb.
+template <class GemmArgsT>
+__device__ __forceinline__ long long urow_off(const GemmArgsT& a, int k, int b, int s) {
+  return ((long long)k * a.uns + (a.upos ? b : s)) * a.nvsp;
+}
+
 __device__ __forceinline__ double block_sum256(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

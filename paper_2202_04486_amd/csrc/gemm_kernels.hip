@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         const int vs = blk0 * CB + col;
         upre_s[q] = make_float2(0.f, 0.f);
         if (i < MB * NW && row < a.nb && vs < a.nvs && s_idx[row] >= 0)
-          upre_s[q] = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
+          upre_s[q] = a.Uf[urow_off(a, k, row, s_idx[row]) + vs];
       }
     }
     if constexpr (KIND == GK_FUSED && C::S == 1) {
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
           const int row = mt * 16 + lq * 4 + e, vs = (blk0 + nt_w) * CB + lr;
           upre[t][e] = make_float2(0.f, 0.f);
           if (row < a.nb && vs < a.nvs && s_idx[row] >= 0)
-            upre[t][e] = a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs];
+            upre[t][e] = a.Uf[urow_off(a, k, row, s_idx[row]) + vs];
         }
       }
     }
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int row = (rt0 + t) * 16 + lq * 4 + e, vs = blk0 * CB + nt_w * 16 + lr;
         const int s = row < a.nb ? max(s_idx[row], 0) : 0;
-        uv[t][e] = a.Uf[((size_t)k * a.ns + s) * a.nvsp + min(vs, a.nvsp - 1)];
+        uv[t][e] = a.Uf[urow_off(a, k, row < a.nb ? row : 0, s) + min(vs, a.nvsp - 1)];
       }
     double lpart = 0.0;
 #pragma unroll
@@ -899,7 +899,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   auto load_u = [&](int k, int cg) -> float2 {
     const int vs = cg * CB + ucol;
     if (urow < a.nb && vs < a.nvs && s_idx[urow] >= 0)
-      return a.Uf[((size_t)k * a.ns + s_idx[urow]) * a.nvsp + vs];
+      return a.Uf[urow_off(a, k, urow, s_idx[urow]) + vs];
     return make_float2(0.f, 0.f);
   };
   auto stage_d = [&](int k) {   // D_{b,k} rows -> LDS

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs a) {
         float2 z = make_float2(acc_re[t][e], acc_im[t][e]);
         if constexpr (KIND == GK_FUSED) {
           if (ok) {
-            z = csub(z, a.Uf[((size_t)k * a.ns + s_idx[row]) * a.nvsp + vs]);
+            z = csub(z, a.Uf[urow_off(a, k, row, s_idx[row]) + vs]);
             lpart += (k == 0 || 2 * k == a.nt ? 1.0 : 2.0) * ((double)z.x * z.x + (double)z.y * z.y);
           } else {
             z = make_float2(0.f, 0.f);
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
   auto load_u = [&](int k, int cg) -> float2 {
     const int vs = cg * CB + ucol;
     if (urow < a.nb && vs < a.nvs && s_idx[urow] >= 0)
-      return a.Uf[((size_t)k * a.ns + s_idx[urow]) * a.nvsp + vs];
+      return a.Uf[urow_off(a, k, urow, s_idx[urow]) + vs];
     return make_float2(0.f, 0.f);
   };
   // D_{b,k} -> split planes; returns the (fp16) scale and its inverse
@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       for (int e = 0; e < 4; ++e) {
         const int row = (rt0 + t) * 16 + lq * 4 + e, vs = blk0 * CB + nt_w * 16 + lr;
         const int s = row < a.nb ? max(s_idx[row], 0) : 0;
-        uv[t][e] = a.Uf[((size_t)k * a.ns + s) * a.nvsp + min(vs, a.nvsp - 1)];
+        uv[t][e] = a.Uf[urow_off(a, k, row < a.nb ? row : 0, s) + min(vs, a.nvsp - 1)];
       }
 #pragma unroll
     for (int t = 0; t < TPC; ++t) {

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(GV_THREADS) void k_gemv(GemmArgs a) {
         const int ii = i + r;
         if constexpr (KIND == GK_FUSED) {
           if (src[r] >= 0) {
-            z = csub(z, a.Uf[((long long)k * a.ns + src[r]) * a.nvsp]);
+            z = csub(z, a.Uf[urow_off(a, k, ii, src[r])]);
             lpart += wk * ((double)z.x * z.x + (double)z.y * z.y);
           } else {
             z = make_float2(0.f, 0.f);

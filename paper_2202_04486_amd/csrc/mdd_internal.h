@@ -33,6 +33,7 @@ struct ReduceArgs {
   const double* oob;      // [ns] per-source out-of-band energy (already / (2 nt))
   const int32_t* idx;
   int nb, ns;
+  int oob_pos;            // 1: oob[b] for batch entry b (staged data), else oob[idx[b]]
   const double* gn_part;
   int n_gn;
   double* loss_out;
@@ -85,6 +86,8 @@ struct GemmArgs {
   // Rows of D per frequency in Df (ns, or nb_max for staged batch rows) and where batch
   // entry b finds its row: 0 = row idx[b] (resident spectra), 1 = row b (staged).
   int dns, dpos;
+  // The same for the rows of U_k (uns rows per frequency; upos 1 = staged row b).
+  int uns, upos;
   // Single virtual source (launch_gemv): row groups per frequency and their adjoint
   // partials [nf][P][nrp / 2] (receiver pairs).
   int P;

@@ -11,7 +11,8 @@ namespace {
 
 constexpr int RED_THREADS = 1024;
 
-// loss = scale * sum(loss partials) + sum_b oob[idx[b]];  gnorm2 = sum(gnorm partials).
+// loss = scale * sum(loss partials) + sum_b oob[idx[b]] (oob[b] for staged data);
+// gnorm2 = sum(gnorm partials).
 // The per-source constants are gathered by one thread each (no serial chain of
 // dependent loads) and added in batch order.
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(ReduceArgs a) {
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ReduceArgs a) {
     double o = 0.0;
     if (a.oob) {
       const int s = a.idx[threadIdx.x];
-      if (s >= 0 && s < a.ns) o = a.oob[s];
+      if (s >= 0 && s < a.ns) o = a.oob[a.oob_pos ? threadIdx.x : s];
     }
     s_oob[threadIdx.x] = o;
   }

@@ -18,12 +18,13 @@ PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3, "fp32_cgemm": 4}
 FLAG_STORE_RF = 1
 FLAG_FULL_GRAD = 2
 FLAG_STREAM_KERNEL = 4
+FLAG_STREAM_DATA = 8
 OPT = {"sgd": 0, "adam": 1, "nsgd": 2}
 KC_NAMES = ("fft_model", "gemm", "update", "reduce", "data_fft", "reciprocity")
 
 # Entry points the header declares (checked by the test-suite against the .so).
 EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_plan_set_stream",
-           "mdd_set_kernel", "mdd_stage_kernel", "mdd_set_data", "mdd_set_mask", "mdc_forward",
+           "mdd_set_kernel", "mdd_stage_kernel", "mdd_set_data", "mdd_stage_data", "mdd_set_mask", "mdc_forward",
            "mdc_adjoint", "mdc_forward_rec", "mdc_adjoint_rec",
            "mdd_stoch_grad", "mdd_stoch_grad_noalloc", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
@@ -73,6 +74,7 @@ def load() -> ctypes.CDLL:
         "mdd_set_kernel": (_I32, [_P, _P]),
         "mdd_stage_kernel": (_I32, [_P, _P, _I32]),
         "mdd_set_data": (_I32, [_P, _P]),
+        "mdd_stage_data": (_I32, [_P, _P, _I32]),
         "mdd_set_mask": (_I32, [_P, _P]),
         "mdc_forward": (_I32, [_P, _P, _P, _I32, _P]),
         "mdc_adjoint": (_I32, [_P, _P, _P, _I32, _P]),

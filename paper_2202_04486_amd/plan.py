@@ -42,7 +42,7 @@ class Plan:
     (float32 with four real products per complex one, for comparison)."""
 
     def __init__(self, ns, nr, nvs, nt, nf, nb_max, precision="fp32", store_rf=False,
-                 device=None, full_grad=False, stream_kernel=False):
+                 device=None, full_grad=False, stream_kernel=False, stream_data=False):
         self.lib = load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
@@ -52,8 +52,10 @@ class Plan:
         self.dims = make_dims(ns, nr, nvs, nt, nf, nb_max, precision,
                               (native.FLAG_STORE_RF if store_rf else 0) |
                               (native.FLAG_FULL_GRAD if full_grad else 0) |
-                              (native.FLAG_STREAM_KERNEL if stream_kernel else 0))
+                              (native.FLAG_STREAM_KERNEL if stream_kernel else 0) |
+                              (native.FLAG_STREAM_DATA if stream_data else 0))
         self.stream_kernel = stream_kernel
+        self.stream_data = stream_data
         nbytes = workspace_bytes(self.dims)
         if nbytes == 0:
             raise MddError("mdd_workspace_bytes", native.MDD_ESHAPE)
@@ -106,6 +108,14 @@ class Plan:
         if d_rows.dim() != 3 or d_rows.shape[1:] != (self.nr, self.nt) or not d_rows.is_contiguous():
             raise ValueError(f"d_rows must be contiguous [nb][{self.nr}][{self.nt}]")
         self._call("mdd_stage_kernel", _ptr(d_rows), int(d_rows.shape[0]))
+
+    def mdd_stage_data(self, u_rows):
+        """Data rows of the next batch (stream_data=True): u_rows [nb][nvs][nt], row b
+        the source that the next call's idx[b] names."""
+        _need(u_rows, "u_rows", None, torch.float32, self.device)
+        if u_rows.dim() != 3 or u_rows.shape[1:] != (self.nvs, self.nt) or not u_rows.is_contiguous():
+            raise ValueError(f"u_rows must be contiguous [nb][{self.nvs}][{self.nt}]")
+        self._call("mdd_stage_data", _ptr(u_rows), int(u_rows.shape[0]))
 
     def mdd_set_data(self, u):
         _need(u, "u", (self.ns, self.nvs, self.nt), torch.float32, self.device)

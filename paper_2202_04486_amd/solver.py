@@ -204,36 +204,49 @@ class FullGradientMDD:
 
 
 class StreamedKernel:
-    """The kernel d [ns][nr][nt] float32 in pinned host memory, streamed a batch at a
-    time to a plan made with stream_kernel=True.
+    """The kernel d [ns][nr][nt] float32 (and, for a plan made with stream_data=True, the
+    up-going data u [ns][nvs][nt]) in pinned host memory, streamed a batch at a time to a
+    plan made with stream_kernel=True.
 
     prefetch(idx) starts copying the rows idx[b] into one of two device buffers on a
-    side stream (default priority); stage(nb) makes the caller's current stream wait for
+    side stream (default priority); stage() makes the caller's current stream wait for
     that copy and stages the rows on the plan, so the next mdd_step / mdd_stoch_grad on
     this batch reads them.  A buffer is refilled only after the stream that staged it
     has passed the staging (an event), so the copy of batch j + 1 overlaps step j."""
 
-    def __init__(self, plan: Plan, d_host: torch.Tensor):
+    def __init__(self, plan: Plan, d_host: torch.Tensor, u_host: torch.Tensor | None = None):
         if not plan.stream_kernel:
             raise ValueError("StreamedKernel needs a plan made with stream_kernel=True")
-        shape = (plan.ns, plan.nr, plan.nt)
-        if tuple(d_host.shape) != shape or d_host.dtype != torch.float32 or d_host.is_cuda:
-            raise ValueError(f"d_host must be a float32 host tensor of shape {shape}")
-        if not d_host.is_pinned():
-            pinned = torch.empty(shape, dtype=torch.float32, pin_memory=True)
-            pinned.copy_(d_host)
-            d_host = pinned
+        if plan.stream_data and u_host is None:
+            raise ValueError("a plan made with stream_data=True needs u_host")
+        if u_host is not None and not plan.stream_data:
+            raise ValueError("u_host needs a plan made with stream_data=True")
         self.plan = plan
-        self.d = d_host.contiguous()
+        self.d = self._pinned(d_host, (plan.ns, plan.nr, plan.nt), "d_host")
+        self.u = None if u_host is None else self._pinned(u_host, (plan.ns, plan.nvs, plan.nt),
+                                                          "u_host")
         dev = plan.device
         self.buf = [torch.empty((plan.nb_max, plan.nr, plan.nt), dtype=torch.float32, device=dev)
                     for _ in range(2)]
+        self.ubuf = None if self.u is None else [
+            torch.empty((plan.nb_max, plan.nvs, plan.nt), dtype=torch.float32, device=dev)
+            for _ in range(2)]
         self.copy_stream = torch.cuda.Stream(dev)
         self.ready = [torch.cuda.Event() for _ in range(2)]
         self.free = [torch.cuda.Event() for _ in range(2)]
         self.nb = [0, 0]
         self.fill = 0      # buffer the next prefetch writes
         self.use = 0       # buffer the next stage reads
+
+    @staticmethod
+    def _pinned(x: torch.Tensor, shape, name) -> torch.Tensor:
+        if tuple(x.shape) != shape or x.dtype != torch.float32 or x.is_cuda:
+            raise ValueError(f"{name} must be a float32 host tensor of shape {shape}")
+        if not x.is_pinned():
+            pinned = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+            pinned.copy_(x)
+            x = pinned
+        return x.contiguous()
 
     def prefetch(self, idx) -> None:
         idx = np.asarray(idx, dtype=np.int64).ravel()
@@ -246,6 +259,8 @@ class StreamedKernel:
             for b, src in enumerate(idx):
                 if 0 <= src < self.plan.ns:   # other entries are zero sources: row unused
                     self.buf[slot][b].copy_(self.d[src], non_blocking=True)
+                    if self.u is not None:
+                        self.ubuf[slot][b].copy_(self.u[src], non_blocking=True)
             self.ready[slot].record(s)
         self.nb[slot] = int(idx.size)
         self.fill ^= 1
@@ -255,6 +270,7 @@ class StreamedKernel:
         cur = torch.cuda.current_stream(self.plan.device)
         cur.wait_event(self.ready[slot])
         self.plan.mdd_stage_kernel(self.buf[slot][:self.nb[slot]])
+        if self.u is not None:
+            self.plan.mdd_stage_data(self.ubuf[slot][:self.nb[slot]])
         self.free[slot].record(cur)
         self.use ^= 1
-

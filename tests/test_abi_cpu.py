@@ -76,10 +76,25 @@ def test_streamed_kernel_flag_keeps_only_the_batch_rows(lib):
     assert b > 0
 
 
+def test_streamed_data_workspace_does_not_grow_with_ns(lib):
+    """MDD_FLAG_STREAM_KERNEL | MDD_FLAG_STREAM_DATA: only the batch's kernel and data rows
+    are kept, so the workspace is the same for 200 sources and for a million; ns above
+    4096 needs a streamed kernel."""
+    f = native.FLAG_STREAM_KERNEL | native.FLAG_STREAM_DATA
+    a = native.workspace_bytes(dims(ns=200, nb_max=8, flags=f))
+    b = native.workspace_bytes(dims(ns=1 << 20, nb_max=8, flags=f))
+    assert a == b > 0
+    c = native.workspace_bytes(dims(ns=8192, nb_max=8, flags=native.FLAG_STREAM_KERNEL))
+    assert c > a                                   # the data spectra of every source
+    assert native.workspace_bytes(dims(ns=8192, nb_max=8)) == 0
+    assert native.workspace_bytes(dims(ns=(1 << 20) + 1, nb_max=8, flags=f)) == 0
+    assert native.workspace_bytes(dims(nr=5000, flags=f)) == 0
+
+
 @pytest.mark.parametrize("kw", [dict(nf=66), dict(nt=100), dict(nt=2048), dict(nb_max=33),
                                 dict(ns=100, nb_max=65), dict(ns=0), dict(nr=-1), dict(nf=0),
                                 dict(precision=5), dict(precision=-1), dict(flags=8), dict(flags=6),
-                                dict(nvs=5000)])
+                                dict(flags=16), dict(flags=14), dict(nvs=5000), dict(ns=5000)])
 def test_invalid_dims_rejected(lib, kw):
     assert native.workspace_bytes(dims(**kw)) == 0
     out = ctypes.c_void_p()
@@ -112,6 +127,7 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.mdd_set_kernel(None, p) == E
     assert lib.mdd_stage_kernel(None, p, 1) == E
     assert lib.mdd_set_data(None, p) == E
+    assert lib.mdd_stage_data(None, p, 1) == E
     assert lib.mdd_set_mask(None, p) == E
     assert lib.mdc_forward(None, p, p, 1, p) == E
     assert lib.mdc_adjoint(None, p, p, 1, p) == E

@@ -150,3 +150,116 @@ def test_staged_reciprocity_operators_equal_resident(nb):
     st.mdd_stage_kernel(T(d[idx]))
     assert torch.equal(res.mdc_forward_rec(T(r), it), st.mdc_forward_rec(T(r), it))
     assert torch.equal(res.mdc_adjoint_rec(T(u[idx]), it), st.mdc_adjoint_rec(T(u[idx]), it))
+
+
+def streamed_data_plan(nb_max, nf, ns, nr, nvs, nt, precision="fp32", store_rf=False, onset=None):
+    from paper_2202_04486_amd.plan import Plan
+    plan = Plan(ns, nr, nvs, nt, nf, nb_max, precision=precision, store_rf=store_rf,
+                stream_kernel=True, stream_data=True)
+    if onset is not None:
+        plan.mdd_set_mask(T(onset, torch.int32))
+    return plan
+
+
+@pytest.mark.parametrize("nvs,nb,prec", CASES, ids=[f"nvs{a}-nb{b}-{c}" for a, b, c in CASES])
+def test_staged_data_equals_resident(nvs, nb, prec):
+    """MDD_FLAG_STREAM_DATA: the data rows and their out-of-band energies staged per batch
+    beside the kernel rows give bitwise the resident plan's gradient, loss and step."""
+    ns, nr, nt, nf = 70, 53, 256, 100
+    d, u, r = random_case(ns, nr, nvs, nt, seed=nb + nvs + 1)
+    res = make_plan(d, u, nb_max=nb, nf=nf, precision=prec)
+    st = streamed_data_plan(nb, nf, ns, nr, nvs, nt, precision=prec)
+    idx = batch(ns, nb, seed=nb + 2)
+    idx[nb // 2] = idx[0]                                    # a repeated source
+    it = T(idx, torch.int32)
+    st.mdd_stage_kernel(T(d[idx]))
+    st.mdd_stage_data(T(u[idx]))
+    a = res.mdd_stoch_grad(T(r), it)
+    b = st.mdd_stoch_grad(T(r), it)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    Ra, Rb = T(r), T(r)
+    la = res.mdd_step(Ra, it, opt="sgd", lr=1e-4)[0]
+    lb = st.mdd_step(Rb, it, opt="sgd", lr=1e-4)[0]
+    assert torch.equal(Ra, Rb) and torch.equal(la, lb)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    tol = 1e-5 if prec == "fp32" else 1e-3
+    assert relerr(H(b[0]), go) <= tol
+    assert abs(b[1].item() - lo) <= tol * lo
+
+
+def test_staged_data_state_errors():
+    from paper_2202_04486_amd import MddError
+    ns, nr, nvs, nt, nf, nb = 20, 16, 16, 128, 65, 8
+    d, u, r = random_case(ns, nr, nvs, nt, seed=19)
+    st = streamed_data_plan(nb, nf, ns, nr, nvs, nt)
+    idx = batch(ns, nb, seed=3)
+    it = T(idx, torch.int32)
+    with pytest.raises(MddError):                 # the data are not resident on this plan
+        st.mdd_set_data(T(u))
+    st.mdd_stage_kernel(T(d[idx]))
+    with pytest.raises(MddError):                 # no data rows staged yet
+        st.mdd_stoch_grad(T(r), it)
+    st.mdd_stage_data(T(u[idx[:5]]))
+    with pytest.raises(MddError):                 # the data rows are not the batch's length
+        st.mdd_stoch_grad(T(r), it)
+    st.mdd_stage_data(T(u[idx]))
+    G, loss, _ = st.mdd_stoch_grad(T(r), it)
+    lo, go = freq.batch_loss_grad(d, r, u, idx, nf)
+    assert relerr(H(G), go) <= 1e-5
+    other = streamed_plan(d, u, nb, nf)            # kernel rows only: no data rows to stage
+    with pytest.raises(MddError):
+        other.mdd_stage_data(T(u[idx]))
+
+
+def test_out_of_core_beyond_4096_sources():
+    """8192 sources, more than a resident plan takes: the kernel and the data stay in
+    pinned host memory and only each batch's rows reach the device.  Batches drawn over
+    the whole index range; each gradient and loss against the oracle on the batch's rows,
+    then Adam steps streamed one batch ahead against the oracle's trajectory."""
+    from paper_2202_04486_amd.solver import StreamedKernel
+    ns, nr, nvs, nt, nf, nb = 8192, 64, 64, 256, 100, 64
+    print(f"out of core: ns={ns} nr={nr} nvs={nvs} nt={nt} nf={nf} nb={nb}", flush=True)
+    d, u = synth.random_arrays(31, (ns, nr, nt), (ns, nvs, nt), dtype=np.float32)
+    r = synth.random_arrays(32, (nr, nvs, nt))[0]
+    r = r.astype(np.float32).astype(np.float64)
+    onset = synth.random_onsets(nr, nvs, nt, seed=33)
+    st = streamed_data_plan(nb, nf, ns, nr, nvs, nt, store_rf=True, onset=onset)
+    ks = StreamedKernel(st, torch.from_numpy(d), torch.from_numpy(u))
+    perm = np.random.default_rng(34).permutation(ns)
+    bs = [np.sort(perm[j * nb:(j + 1) * nb]).astype(np.int32) for j in range(4)]
+    bs.append(np.sort(np.concatenate([perm[-nb // 2:], [0, ns - 1]] +
+                                     [perm[:nb // 2 - 2]])).astype(np.int32))
+    assert min(b.min() for b in bs) == 0 and max(b.max() for b in bs) == ns - 1
+    d64 = lambda b: d[b].astype(np.float64)               # noqa: E731
+    u64 = lambda b: u[b].astype(np.float64)               # noqa: E731
+    for b in bs:                                          # gradients at a fixed model
+        ks.prefetch(b)
+        ks.stage()
+        G, loss, _ = st.mdd_stoch_grad(T(r), T(b, torch.int32))
+        lo, go = freq.batch_loss_grad(d64(b), r, u64(b), np.arange(nb), nf)
+        go = optim.apply_mask(go, onset)
+        assert relerr(H(G), go) <= 1e-5
+        assert abs(loss.item() - lo) <= 1e-5 * lo
+    st.mdd_invalidate_model_spectra()
+    R = torch.zeros(nr, nvs, nt, device="cuda")
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    ro = np.zeros((nr, nvs, nt))
+    mo, vo = np.zeros_like(ro), np.zeros_like(ro)
+    _, g0 = freq.batch_loss_grad(d64(bs[0]), ro, u64(bs[0]), np.arange(nb), nf)
+    eps = 1e-2 * float(np.sqrt(np.mean(optim.apply_mask(g0, onset) ** 2)))
+    ks.prefetch(bs[0])
+    for t, b in enumerate(bs, start=1):
+        ks.stage()
+        if t < len(bs):
+            ks.prefetch(bs[t])
+        st.mdd_step(R, T(b, torch.int32), opt="adam", lr=1e-2, s0=m, s1=v, t=t, eps=eps)
+        _, g = freq.batch_loss_grad(d64(b), ro, u64(b), np.arange(nb), nf)
+        ro, mo, vo = optim.adam(ro, mo, vo, optim.apply_mask(g, onset), t, 1e-2, eps=eps,
+                                onset=onset)
+    torch.cuda.synchronize()
+    assert relerr(H(m), mo) <= 1e-5
+    assert relerr(H(v), vo) <= 1e-5
+    diff = np.abs(H(R) - ro)
+    assert np.linalg.norm(diff) <= 1e-4 * np.linalg.norm(ro)
+    assert diff.max() <= 1e-2 * 1e-2
