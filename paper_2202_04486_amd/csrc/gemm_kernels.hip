@@ -565,6 +565,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   }
 }
 
+// s <- s + x with the rounding error of that addition added to the compensation e
+// (Dekker's Fast2Sum on each lane value: the error term is exact when |s| >= |x|,
+// which holds once the running total dominates one chunk's sum; when it does not,
+// the sum itself is still the rounded one).
+__device__ __forceinline__ void two_sum(floatx4& s, floatx4& e, const floatx4& x) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float t = s[i] + x[i];
+    e[i] += x[i] - (t - s[i]);
+    s[i] = t;
+  }
+}
+
 // Float32 fused products for 33..64 batch rows: a warp-specialised workgroup of
 // twelve waves.  Four loader waves keep three 64-receiver chunks of R_k (96 KB)
 // in flight in their registers and pass each through a two-slot LDS ring; eight
@@ -661,13 +674,17 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
         *reinterpret_cast<float4*>(s_d + sl * DSL + b * WF_DP + rr) = v;
       }
     };
-    // per tile: (re, im) and the third accumulator of cmac3 (unused by the cgemm form)
-    floatx4 ar[TPC], ai[TPC], a3[TPC];
+    // per tile: (re, im) and the third accumulator of cmac3 (unused by the cgemm form),
+    // and their compensation terms
+    floatx4 ar[TPC], ai[TPC], a3[TPC], er[TPC], ei[TPC], e3[TPC];
 #pragma unroll
     for (int t = 0; t < TPC; ++t) {
       ar[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       ai[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       a3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      er[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ei[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      e3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     load_d(0);
     __syncthreads();
@@ -679,20 +696,41 @@ __global__ __launch_bounds__(WF_THREADS) void k_gemm_ws(GemmArgs a) {
       const int sl = c & 1;
       const float2* ring = s_ring + sl * RING + lq * WF_RP + nt_w * 16 + lr;
       const float2* dsl = s_d + sl * DSL + (rt0 * 16 + lr) * WF_DP + lq;
+      // two-level sum: each chunk's 16 k-steps start from zero and the chunk's sum is
+      // added to the total with its rounding error carried in a compensation term
+      // (TwoSum), so the products' rounding grows with the chunk length, not with nr
+      floatx4 cr[TPC], ci[TPC], c3[TPC];
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        cr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        ci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        c3[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {  // rows past nr are zeros in both operands
         const float2 bv = ring[ks * 4 * WF_RP];
         const float bsum = bv.x + bv.y;
 #pragma unroll
         for (int t = 0; t < TPC; ++t)
-          cmac<PREC>(dsl[t * 16 * WF_DP + ks * 4], bv, bsum, ar[t], ai[t], a3[t]);
+          cmac<PREC>(dsl[t * 16 * WF_DP + ks * 4], bv, bsum, cr[t], ci[t], c3[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < TPC; ++t) {
+        two_sum(ar[t], er[t], cr[t]);
+        two_sum(ai[t], ei[t], ci[t]);
+        two_sum(a3[t], e3[t], c3[t]);
       }
       stage_d(sl ^ 1, c + 1);  // the next chunk into the slot chunk c - 1 used
       load_d(c + 2);
       __syncthreads();
     }
 #pragma unroll
-    for (int t = 0; t < TPC; ++t) cmac_finish<PREC>(ar[t], ai[t], a3[t]);
+    for (int t = 0; t < TPC; ++t) {
+      ar[t] += er[t];
+      ai[t] += ei[t];
+      a3[t] += e3[t];
+      cmac_finish<PREC>(ar[t], ai[t], a3[t]);
+    }
 
     if constexpr (KIND == GK_FWD) {  // P_k = D_b R_k -> batch spectra
 #pragma unroll
