@@ -270,3 +270,51 @@ def test_mdc_rec_needs_square_models():
         plan.mdc_forward_rec(T(r), it)
     with pytest.raises(MddError):
         plan.mdc_adjoint_rec(T(u[:4]), it)
+
+
+def test_patch3d_fp32_gradient_after_250_steps():
+    """The 3D patch's geometry with 1600 receivers (so the products sum over 1600
+    receivers), 256 sources and 32 virtual sources, noise-free data u = P+ R_true made by
+    the oracle, and 250 steps of fp32 Adam (batches of 64, eps 1e-8, the bench's setting,
+    mask on), as many as ten epochs of the full patch.  The model fits
+    the data and the gradient shrinks to a few per cent of its size at R = 0, while the
+    rounding of D_b R_k - U_b stays at the data's scale.  The gradient at that model must
+    still match the oracle to 1e-5: the products' compensated two-level sum keeps that
+    rounding small enough (one float32 accumulator over the 1600 receivers did not)."""
+    from paper_2202_04486_amd.plan import Plan
+    wl = synth.WORKLOADS["patch3d"].replace(ns=256, nvs=32, vs_first=784)
+    dev = torch.device("cuda", 0)
+    xs, xr = synth.positions(wl.ns, wl), synth.positions(wl.nr, wl)
+    xv = synth.vs_positions(wl)
+    d = synth.cube_on_device(xs, xr, wl, synth.down_events(wl), dev)
+    r_true = synth.cube_on_device(xr, xv, wl, synth.reflection_events(wl), dev)
+    onset = synth.onsets(wl)
+    d64 = H(d)
+    u = f32(freq.mdc(d64, H(r_true), wl.nf))
+    del r_true
+    plan = Plan(wl.ns, wl.nr, wl.nvs, wl.nt, wl.nf, wl.nb, store_rf=True)
+    plan.mdd_set_kernel(d)
+    plan.mdd_set_data(T(u))
+    plan.mdd_set_mask(T(onset, torch.int32))
+    R = torch.zeros(wl.nr, wl.nvs, wl.nt, device=dev)
+    m, v = torch.zeros_like(R), torch.zeros_like(R)
+    perms = synth.epoch_permutations(wl, 64)
+    t = 0
+    for e in range(63):
+        for b in optim.batches(perms[e], wl.nb):
+            t += 1
+            plan.mdd_step(R, T(b, torch.int32), opt="adam", lr=1e-2, s0=m, s1=v, t=t)
+    b0 = optim.batches(perms[63], wl.nb)[0]
+    G, _, _ = plan.mdd_stoch_grad(R, T(b0, torch.int32))
+    _, go = freq.batch_loss_grad(d64, H(R), u, b0, wl.nf)
+    go = optim.apply_mask(go, onset)
+    _, g0 = freq.batch_loss_grad(d64, np.zeros_like(go), u, b0, wl.nf)
+    g0 = optim.apply_mask(g0, onset)
+    e = relerr(H(G), go)
+    ratio = np.linalg.norm(go) / np.linalg.norm(g0)
+    print(f"patch3d fp32, 256 sources, 32 virtual sources, after {t} steps: gradient {ratio:.3f} of its size "
+          f"at R = 0, rel err {e:.3e}, err over the gradient at R = 0 {e * ratio:.2e}")
+    assert ratio < 0.05                                 # the model has fitted the data
+    assert e <= 1e-5
+    plan.close()
+    torch.cuda.empty_cache()
