@@ -50,6 +50,15 @@ struct SplitT {
   }
 };
 
+// Two values split at once (one packed conversion for the two hi halves and one for
+// the two lo halves), bf16 only.
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split2_bf16(float x0, float x1, bf16x2& hi, bf16x2& lo) {
+  const floatx2 x = {x0, x1};
+  hi = __builtin_convertvector(x, bf16x2);
+  lo = __builtin_convertvector(x - __builtin_convertvector(hi, floatx2), bf16x2);
+}
+
 // The 16x16x16 shape (four k values per lane), for products over at most 16
 // batch rows.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -87,6 +96,28 @@ __device__ __forceinline__ void cmma3(const V& arh, const V& arl, const V& aih, 
   im = T::mma(aih, brh, im);
   im = T::mma(aih, brl, im);
   im = T::mma(ail, brh, im);
+}
+
+// acc += A * B with the imaginary part of A given negated (nai = -Im A, which the
+// operand staging supplies at no cost): Re += ar br + nai bi and Im += ar bi, while the
+// remaining imaginary term nai br goes into u, subtracted once at the end
+// (Im = im - u).  No operand is negated per product.
+template <typename T, typename V>
+__device__ __forceinline__ void cmma3n(const V& arh, const V& arl, const V& naih, const V& nail,
+                                       const V& brh, const V& brl, const V& bih, const V& bil,
+                                       floatx4& re, floatx4& im, floatx4& u) {
+  re = T::mma(arh, brh, re);
+  re = T::mma(arh, brl, re);
+  re = T::mma(arl, brh, re);
+  re = T::mma(naih, bih, re);
+  re = T::mma(naih, bil, re);
+  re = T::mma(nail, bih, re);
+  im = T::mma(arh, bih, im);
+  im = T::mma(arh, bil, im);
+  im = T::mma(arl, bih, im);
+  u = T::mma(naih, brh, u);
+  u = T::mma(naih, brl, u);
+  u = T::mma(nail, brh, u);
 }
 
 // Power-of-two scale bringing max |x| to [2^13, 2^14), and its inverse; the
@@ -762,8 +793,15 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   using V = typename T::V;
   using V2 = typename T::V2;
   constexpr int MB = C::MB, NW = C::NW, KC = C::KCMAX, KSW = C::KSW;
-  constexpr int RRP = NW + 2;                 // ring row pitch (complex values)
-  constexpr int RING = KC * RRP;              // complex values per ring slot
+  constexpr int RRP = NW + 2;                 // fp16 ring row pitch (complex values)
+  constexpr int RING = KC * RRP;              // fp16: complex values per ring slot
+  // bf16: the loader waves split R_k into four planes [re hi, re lo, im hi, im lo] of
+  // [column][receiver] bf16 values, so that each B operand is one 16-byte LDS read and
+  // every value is split once (fp16 keeps float32 values: its per-chunk scale needs the
+  // maximum over all loader waves before any value can be split).
+  constexpr bool SPLIT_RING = !T::F16;
+  constexpr int RKP = KC + 8;                 // split-ring plane row pitch (elements)
+  constexpr int RSLOT = 4 * NW * RKP;         // split ring: elements per slot
   constexpr int NCT = 64 * WS_CW, NLT = 64 * WS_LW;  // compute / loader threads
   constexpr int LPT = KC * NW / 2 / NLT;      // float4 per loader thread per chunk
   constexpr int TPC = C::TPWV * 4 / WS_CW;    // forward 16x16 tiles per compute wave
@@ -774,7 +812,9 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   E* s_dsl = reinterpret_cast<E*>(smem_raw);  // two D slots of C::DSZ elements
   float2* s_ring = reinterpret_cast<float2*>(smem_raw + 2 * sizeof(E) * C::DSZ);
   E* s_rpl = reinterpret_cast<E*>(s_ring);    // residual planes; the ring is free by then
-  static_assert(sizeof(E) * C::RS <= sizeof(float2) * 2 * RING, "residual planes fit the ring");
+  E* s_rsp = reinterpret_cast<E*>(s_ring);    // split ring (bf16)
+  static_assert(sizeof(E) * C::RS <= (SPLIT_RING ? sizeof(E) * 2 * RSLOT : sizeof(float2) * 2 * RING),
+                "residual planes fit the ring");
   __shared__ int s_idx[MB];
   __shared__ long long s_drow[MB];
   __shared__ double s_red[WS_CW];
@@ -850,7 +890,21 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   // loads are unconditional (addresses clamped into the array) so that nothing
   // waits for them before they are written to the ring, where rows beyond nr and
   // blocks beyond nvb become zeros.
+  // bf16 split ring: loader thread li owns column pair 2 (li % 32) and the eight rows
+  // 8 (li / 32) .. + 7 of each chunk: one 16-byte load per row.
+  static_assert(!SPLIT_RING || (LPT == 8 && NLT == (NW / 2) * (KC / 8)), "split-ring mapping");
+  const int lcp = 2 * (li & 31), lrg = 8 * (li >> 5);
+  const bool lblk_ok = blk0 + lcp / CB < a.nvb;
+  const float2* lcol = a.F + ((long long)min(blk0 + lcp / CB, a.nvb - 1) * a.nf + k) * CB + lcp % CB;
   auto issue = [&](float4 (&dst)[LPT], int c) {
+    if constexpr (SPLIT_RING) {
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const int r = min(c * KC + lrg + q, a.nr - 1);
+        dst[q] = *reinterpret_cast<const float4*>(lcol + (long long)r * rowstride);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int i = li + NLT * q;
@@ -862,6 +916,38 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   };
   auto put_ring = [&](const float4 (&src)[LPT], int c) {
     const int slot = c & 1;
+    if constexpr (SPLIT_RING) {
+      float x[4][8];  // column lcp re, im; column lcp + 1 re, im; rows lrg .. lrg + 7
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const bool ok = lblk_ok && c * KC + lrg + q < a.nr;
+        x[0][q] = ok ? src[q].x : 0.f;
+        x[1][q] = ok ? src[q].y : 0.f;
+        x[2][q] = ok ? src[q].z : 0.f;
+        x[3][q] = ok ? src[q].w : 0.f;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // the two columns
+        V ph[2], pl[2];              // [re, im] hi / lo
+#pragma unroll
+        for (int part = 0; part < 2; ++part)
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            bf16x2 hv, lv;
+            split2_bf16(x[2 * h + part][e], x[2 * h + part][e + 1], hv, lv);
+            ph[part][e] = hv[0];
+            ph[part][e + 1] = hv[1];
+            pl[part][e] = lv[0];
+            pl[part][e + 1] = lv[1];
+          }
+        E* dst = s_rsp + slot * RSLOT + (lcp + h) * RKP + lrg;
+        *reinterpret_cast<V*>(dst) = ph[0];
+        *reinterpret_cast<V*>(dst + NW * RKP) = pl[0];
+        *reinterpret_cast<V*>(dst + 2 * NW * RKP) = ph[1];
+        *reinterpret_cast<V*>(dst + 3 * NW * RKP) = pl[1];
+      }
+      return;
+    }
     float m = 0.f;
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
@@ -887,34 +973,77 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     return (off >= 0 ? off : drow0) + (r < a.nr ? r : 0);
   };
   auto d_ok = [&](int b, int r) { return s_drow[b] >= 0 && r < a.nr; };
+  // Each compute thread stages eight consecutive receivers of one batch row per chunk
+  // (64 rows x 8 groups = the 512 compute threads): four 16-byte loads, and one 16-byte
+  // LDS write per plane.  Its row's address is fixed for the item; receivers at or past
+  // nr (only in the last chunk) are zeroed, and a group starting at or past the padded
+  // row length loads receiver 0 instead (always in bounds).
+  static_assert(FPT == 4 && NCT == MB * (KC / 8), "one row and eight receivers per thread");
+  const int db = tid >> 3, dg = (tid & 7) * 8;      // compute threads only
+  const bool drow_ok = compute && s_drow[db] >= 0;
+  const float2* drow_p = a.Df + (compute && s_drow[db] >= 0 ? s_drow[db] : drow0);
   float4 dv[FPT];
   auto load_dfwd = [&](int c) {
+    const int r0 = c * KC + dg;
+    const float4* src = reinterpret_cast<const float4*>(drow_p + (r0 < a.nrp ? r0 : 0));
 #pragma unroll
-    for (int q = 0; q < FPT; ++q) {
-      const int i = tid + NCT * q;
-      dv[q] = *reinterpret_cast<const float4*>(a.Df + d_at(i / (KC / 2), c * KC + 2 * (i % (KC / 2))));
-    }
+    for (int q = 0; q < FPT; ++q) dv[q] = src[q];
   };
   auto stage_dfwd = [&](int sl, float sd, int c) {
+    const int r0 = c * KC + dg;
+    float x[16];
 #pragma unroll
     for (int q = 0; q < FPT; ++q) {
-      const int i = tid + NCT * q;
-      const int b = i / (KC / 2), rr = 2 * (i % (KC / 2)), r = c * KC + rr;
-      float4 v = d_ok(b, r) ? dv[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r + 1 >= a.nr) v.z = v.w = 0.f;
-      put2(dfw(sl, 0, b, rr), v.x * sd, v.z * sd, dfw(sl, 1, b, rr));
-      put2(dfw(sl, 2, b, rr), v.y * sd, v.w * sd, dfw(sl, 3, b, rr));
+      x[4 * q] = dv[q].x;
+      x[4 * q + 1] = dv[q].y;
+      x[4 * q + 2] = dv[q].z;
+      x[4 * q + 3] = dv[q].w;
     }
+    if (!drow_ok || r0 + 8 > a.nr) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (!drow_ok || r0 + e >= a.nr) x[2 * e] = x[2 * e + 1] = 0.f;
+    }
+    V rh, rl, nih, nil;  // nih, nil: -Im D (cmma3n)
+#pragma unroll
+    for (int e = 0; e < 8; e += (T::F16 ? 1 : 2)) {
+      if constexpr (T::F16) {
+        E h, l;
+        T::split(x[2 * e] * sd, h, l);
+        rh[e] = h;
+        rl[e] = l;
+        T::split(-x[2 * e + 1] * sd, h, l);
+        nih[e] = h;
+        nil[e] = l;
+      } else {
+        bf16x2 hv, lv;
+        split2_bf16(x[2 * e], x[2 * e + 2], hv, lv);
+        rh[e] = hv[0];
+        rh[e + 1] = hv[1];
+        rl[e] = lv[0];
+        rl[e + 1] = lv[1];
+        split2_bf16(-x[2 * e + 1], -x[2 * e + 3], hv, lv);
+        nih[e] = hv[0];
+        nih[e + 1] = hv[1];
+        nil[e] = lv[0];
+        nil[e + 1] = lv[1];
+      }
+    }
+    *reinterpret_cast<V*>(dfw(sl, 0, db, dg)) = rh;
+    *reinterpret_cast<V*>(dfw(sl, 1, db, dg)) = rl;
+    *reinterpret_cast<V*>(dfw(sl, 2, db, dg)) = nih;
+    *reinterpret_cast<V*>(dfw(sl, 3, db, dg)) = nil;
   };
 
   // The two roles run separate loops with the same barriers (2 + nc of them), so
   // that the loaders' in-flight registers and the compute waves' accumulators
   // are not live at the same time in either.
-  floatx4 acc_re[TPC], acc_im[TPC];
+  floatx4 acc_re[TPC], acc_im[TPC], acc_u[TPC];
 #pragma unroll
   for (int t = 0; t < TPC; ++t) {
     acc_re[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     acc_im[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    acc_u[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
   if (compute) {
     // prologue: D chunk 0 staged, chunk 1 in flight
@@ -928,41 +1057,51 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       const int sl = c & 1;
       const int len = min(KC, a.nr - c * KC);
       const float2 sd = sdk, sr = scale_of(s_rmax[sl], WS_LW);
-      floatx4 cre[TPC], cim[TPC];
+      floatx4 cre[TPC], cim[TPC], cu[TPC];
 #pragma unroll
       for (int t = 0; t < TPC; ++t) {
         if constexpr (T::F16) {
           cre[t] = floatx4{0.f, 0.f, 0.f, 0.f};
           cim[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          cu[t] = floatx4{0.f, 0.f, 0.f, 0.f};
         } else {
           cre[t] = acc_re[t];
           cim[t] = acc_im[t];
+          cu[t] = acc_u[t];
         }
       }
       const float2* ring = s_ring + sl * RING + nt_w * 16 + lr;
+      const E* rsp = s_rsp + sl * RSLOT + (nt_w * 16 + lr) * RKP + lq * 8;
 #pragma unroll
       for (int q = 0; q < KSW; ++q) {
         if (q * 32 < len) {
           V brh, brl, bih, bil;
+          if constexpr (SPLIT_RING) {
+            brh = *reinterpret_cast<const V*>(rsp + q * 32);
+            brl = *reinterpret_cast<const V*>(rsp + NW * RKP + q * 32);
+            bih = *reinterpret_cast<const V*>(rsp + 2 * NW * RKP + q * 32);
+            bil = *reinterpret_cast<const V*>(rsp + 3 * NW * RKP + q * 32);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float2 x = ring[(q * 32 + lq * 8 + e) * RRP];
-            E h, l;
-            T::split(x.x * sr.x, h, l);
-            brh[e] = h;
-            brl[e] = l;
-            T::split(x.y * sr.x, h, l);
-            bih[e] = h;
-            bil[e] = l;
+            for (int e = 0; e < 8; ++e) {
+              const float2 x = ring[(q * 32 + lq * 8 + e) * RRP];
+              E h, l;
+              T::split(x.x * sr.x, h, l);
+              brh[e] = h;
+              brl[e] = l;
+              T::split(x.y * sr.x, h, l);
+              bih[e] = h;
+              bil[e] = l;
+            }
           }
 #pragma unroll
           for (int t = 0; t < TPC; ++t) {
             const int row = (rt0 + t) * 16 + lr, col = q * 32 + lq * 8;
             const V arh = *reinterpret_cast<const V*>(dfw(sl, 0, row, col));
             const V arl = *reinterpret_cast<const V*>(dfw(sl, 1, row, col));
-            const V aih = *reinterpret_cast<const V*>(dfw(sl, 2, row, col));
-            const V ail = *reinterpret_cast<const V*>(dfw(sl, 3, row, col));
-            cmma3<T>(arh, arl, aih, ail, brh, brl, bih, bil, cre[t], cim[t]);
+            const V naih = *reinterpret_cast<const V*>(dfw(sl, 2, row, col));
+            const V nail = *reinterpret_cast<const V*>(dfw(sl, 3, row, col));
+            cmma3n<T>(arh, arl, naih, nail, brh, brl, bih, bil, cre[t], cim[t], cu[t]);
           }
         }
       }
@@ -970,10 +1109,11 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       for (int t = 0; t < TPC; ++t) {
         if constexpr (T::F16) {
           acc_re[t] += (cre[t] * sd.y) * sr.y;
-          acc_im[t] += (cim[t] * sd.y) * sr.y;
+          acc_im[t] += ((cim[t] - cu[t]) * sd.y) * sr.y;
         } else {
           acc_re[t] = cre[t];
           acc_im[t] = cim[t];
+          acc_u[t] = cu[t];
         }
       }
       // the next D chunk into the other slot (last read by chunk c - 1); unconditional
@@ -1020,6 +1160,10 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   double lpart = 0.0;
   float rm = 0.f;
   float2 zr[TPC][4];
+  if constexpr (!T::F16) {
+#pragma unroll
+    for (int t = 0; t < TPC; ++t) acc_im[t] -= acc_u[t];
+  }
   if (compute) {
     float2 uv[TPC][4];  // all of this lane's U_b entries in flight at once
 #pragma unroll
@@ -1081,15 +1225,29 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   }
   __syncthreads();  // the last barrier: the ring is no longer used
   const int nrt = (a.nr + 15) / 16;
-  auto load_tile = [&](float2 (&d)[2][8], int mt) {  // clamped: always in bounds
-    const int r = min(mt * 16 + lr, a.nr - 1);
+  // This lane's sixteen batch rows (b = kk * 32 + lq * 8 + e) are the same for every
+  // tile: their offsets from the frequency's first row (32-bit, a rejected row reading
+  // row 0) and whether all of them are real are found once.
+  unsigned aoff[2][8];
+  bool arows_ok = true;
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const long long off = s_drow[kk * 32 + lq * 8 + e];
+      aoff[kk][e] = off >= 0 ? (unsigned)(off - drow0) : 0u;
+      arows_ok = arows_ok && off >= 0;
+    }
+  const float2* dk = a.Df + drow0;
+  auto load_tile = [&](float2 (&d)[2][8], int mt, int zero) {  // clamped: always in bounds
+    const float2* dr = dk + min(mt * 16 + lr, a.nr - 1) + zero;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d[kk][e] = a.Df[d_at(kk * 32 + lq * 8 + e, r)];
+      for (int e = 0; e < 8; ++e) d[kk][e] = dr[aoff[kk][e]];
   };
   float2 dn[2][8];
-  load_tile(dn, min(wave, nrt - 1));
+  load_tile(dn, min(wave, nrt - 1), 0);
 #pragma unroll 1
   for (int mt = wave; mt < nrt; mt += WS_CW + WS_LW) {
     float2 dc[2][8];
@@ -1097,30 +1255,54 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int e = 0; e < 8; ++e) dc[kk][e] = dn[kk][e];
-    load_tile(dn, min(mt + WS_CW + WS_LW, nrt - 1));
     const int r = mt * 16 + lr;
+    if (!arows_ok || r >= a.nr) {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk)
+      for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (!d_ok(kk * 32 + lq * 8 + e, r)) dc[kk][e] = make_float2(0.f, 0.f);
+        for (int e = 0; e < 8; ++e)
+          if (!d_ok(kk * 32 + lq * 8 + e, r)) dc[kk][e] = make_float2(0.f, 0.f);
+    }
     const float2 sd = sdk;
-    V arh[2], arl[2], aih[2], ail[2];
+    V arh[2], arl[2], aih[2], ail[2];  // aih, ail: conj D's -Im = Im D (cmma3n)
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        E h, l;
-        T::split(dc[kk][e].x * sd.x, h, l);
-        arh[kk][e] = h;
-        arl[kk][e] = l;
-        T::split(-dc[kk][e].y * sd.x, h, l);  // conj
-        aih[kk][e] = h;
-        ail[kk][e] = l;
+      for (int e = 0; e < 8; e += (T::F16 ? 1 : 2)) {
+        if constexpr (T::F16) {
+          E h, l;
+          T::split(dc[kk][e].x * sd.x, h, l);
+          arh[kk][e] = h;
+          arl[kk][e] = l;
+          T::split(dc[kk][e].y * sd.x, h, l);
+          aih[kk][e] = h;
+          ail[kk][e] = l;
+        } else {
+          bf16x2 hv, lv;
+          split2_bf16(dc[kk][e].x, dc[kk][e + 1].x, hv, lv);
+          arh[kk][e] = hv[0];
+          arh[kk][e + 1] = hv[1];
+          arl[kk][e] = lv[0];
+          arl[kk][e + 1] = lv[1];
+          split2_bf16(dc[kk][e].y, dc[kk][e + 1].y, hv, lv);
+          aih[kk][e] = hv[0];
+          aih[kk][e + 1] = hv[1];
+          ail[kk][e] = lv[0];
+          ail[kk][e + 1] = lv[1];
+        }
       }
+    // The next tile's A operand is requested only after this tile's values have arrived:
+    // vector-memory loads and stores retire in order under one counter, so a wait for
+    // loads issued after the previous tile's G stores would wait for those stores too.
+    // The empty asm statement takes the last of this tile's values and yields the zero
+    // that the next tile's addresses add, so the compiler cannot issue those loads first.
+    int zero = 0;
+    asm volatile("" : "+v"(zero) : "v"(dc[1][7].x));
+    load_tile(dn, min(mt + WS_CW + WS_LW, nrt - 1), zero);
 #pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {  // not unrolled: the B operands of one column tile at a time
       floatx4 re = floatx4{0.f, 0.f, 0.f, 0.f}, im = floatx4{0.f, 0.f, 0.f, 0.f};
+      floatx4 u = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
         const int b = kk * 32 + lq * 8, col = nt * 16 + lr;
@@ -1128,8 +1310,9 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
         const V brl = *reinterpret_cast<const V*>(rsp(1, col, b));
         const V bih = *reinterpret_cast<const V*>(rsp(2, col, b));
         const V bil = *reinterpret_cast<const V*>(rsp(3, col, b));
-        cmma3<T>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im);
+        cmma3n<T>(arh[kk], arl[kk], aih[kk], ail[kk], brh, brl, bih, bil, re, im, u);
       }
+      im -= u;
       if constexpr (T::F16) {
         re = (re * sd.y) * ss.y;
         im = (im * sd.y) * ss.y;
@@ -1149,8 +1332,10 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
 template <int PREC>
 hipError_t launch_split_ws(const GemmArgs& a, hipStream_t s) {
   using C = SCfg<4, 4>;
-  constexpr size_t sm = 2 * sizeof(typename SplitT<PREC>::E) * C::DSZ +
-                        sizeof(float2) * 2 * C::KCMAX * (C::NW + 2);
+  using E = typename SplitT<PREC>::E;
+  constexpr size_t ring = SplitT<PREC>::F16 ? sizeof(float2) * 2 * C::KCMAX * (C::NW + 2)
+                                            : sizeof(E) * 2 * 4 * C::NW * (C::KCMAX + 8);
+  constexpr size_t sm = 2 * sizeof(E) * C::DSZ + ring;
   const int ncg = (a.nvb + 3) / 4;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_split_ws<PREC>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
