@@ -39,6 +39,25 @@ __device__ __forceinline__ void store_g(const GemmArgsT& a, long long off, float
   *p = v;
 }
 
+// Streaming (non-temporal) accesses for data a launch touches once, R_k read and G
+// written by the product kernels, so that they do not evict the kernel rows D_b, which
+// every column group of a frequency reads again.
+typedef float stream_f4 __attribute__((ext_vector_type(4)));
+typedef float stream_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 stream_load4(const float2* p) {
+  const stream_f4 v = __builtin_nontemporal_load(reinterpret_cast<const stream_f4*>(p));
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+// store_g for the plain case (written over R_k in F) as a streaming store.
+template <class GemmArgsT>
+__device__ __forceinline__ void store_g_stream(const GemmArgsT& a, long long off, float2 v) {
+  if (a.gacc || a.Gout) {
+    store_g(a, off, v);
+  } else {
+    __builtin_nontemporal_store(stream_f2{v.x, v.y}, reinterpret_cast<stream_f2*>(a.F + off));
+  }
+}
+
 // Row of D_k for batch entry b whose source s is valid: s in the resident spectra,
 // b in spectra staged for the batch.
 template <class GemmArgsT>

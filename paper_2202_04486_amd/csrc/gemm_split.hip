@@ -901,7 +901,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
 #pragma unroll
       for (int q = 0; q < LPT; ++q) {
         const int r = min(c * KC + lrg + q, a.nr - 1);
-        dst[q] = *reinterpret_cast<const float4*>(lcol + (long long)r * rowstride);
+        dst[q] = stream_load4(lcol + (long long)r * rowstride);
       }
       return;
     }
@@ -910,8 +910,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       const int i = li + NLT * q;
       const int rr = i / (NW / 2), cp = 2 * (i % (NW / 2));
       const int r = min(c * KC + rr, a.nr - 1), blk = min(blk0 + cp / CB, a.nvb - 1);
-      dst[q] = *reinterpret_cast<const float4*>(a.F + (long long)r * rowstride +
-                                                ((long long)blk * a.nf + k) * CB + cp % CB);
+      dst[q] = stream_load4(a.F + (long long)r * rowstride + ((long long)blk * a.nf + k) * CB + cp % CB);
     }
   };
   auto put_ring = [&](const float4 (&src)[LPT], int c) {
@@ -982,22 +981,24 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
   const int db = tid >> 3, dg = (tid & 7) * 8;      // compute threads only
   const bool drow_ok = compute && s_drow[db] >= 0;
   const float2* drow_p = a.Df + (compute && s_drow[db] >= 0 ? s_drow[db] : drow0);
-  float4 dv[FPT];
-  auto load_dfwd = [&](int c) {
+  // Two chunks in flight: chunk c + 3 is requested when chunk c + 1 is staged, two
+  // chunks of products before it is needed (a miss in L2 is served from farther away).
+  float4 dv[2][FPT];
+  auto load_dfwd = [&](float4 (&d)[FPT], int c) {
     const int r0 = c * KC + dg;
     const float4* src = reinterpret_cast<const float4*>(drow_p + (r0 < a.nrp ? r0 : 0));
 #pragma unroll
-    for (int q = 0; q < FPT; ++q) dv[q] = src[q];
+    for (int q = 0; q < FPT; ++q) d[q] = src[q];
   };
-  auto stage_dfwd = [&](int sl, float sd, int c) {
+  auto stage_dfwd = [&](const float4 (&d)[FPT], int sl, float sd, int c) {
     const int r0 = c * KC + dg;
     float x[16];
 #pragma unroll
     for (int q = 0; q < FPT; ++q) {
-      x[4 * q] = dv[q].x;
-      x[4 * q + 1] = dv[q].y;
-      x[4 * q + 2] = dv[q].z;
-      x[4 * q + 3] = dv[q].w;
+      x[4 * q] = d[q].x;
+      x[4 * q + 1] = d[q].y;
+      x[4 * q + 2] = d[q].z;
+      x[4 * q + 3] = d[q].w;
     }
     if (!drow_ok || r0 + 8 > a.nr) {
 #pragma unroll
@@ -1046,14 +1047,17 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     acc_u[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   }
   if (compute) {
-    // prologue: D chunk 0 staged, chunk 1 in flight
-    load_dfwd(0);
+    // prologue: D chunk 0 staged, chunks 1 and 2 in flight (chunks past the end load
+    // clamped addresses and stage zeros)
+    load_dfwd(dv[0], 0);
+    load_dfwd(dv[1], 1);
     __syncthreads();
-    stage_dfwd(0, sdk.x, 0);
-    load_dfwd(1);  // chunks past the end load clamped addresses and stage zeros
+    stage_dfwd(dv[0], 0, sdk.x, 0);
+    load_dfwd(dv[0], 2);
     __syncthreads();
-#pragma unroll 1
-    for (int c = 0; c < nc; ++c) {
+    // chunk c: its products, then chunk c + 1 staged from buffer b = (c + 1) % 2 and
+    // chunk c + 3 requested into it
+    auto chunk = [&](int c, float4 (&dvb)[FPT]) {
       const int sl = c & 1;
       const int len = min(KC, a.nr - c * KC);
       const float2 sd = sdk, sr = scale_of(s_rmax[sl], WS_LW);
@@ -1118,10 +1122,17 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
       }
       // the next D chunk into the other slot (last read by chunk c - 1); unconditional
       // so that the loads in flight are the same on every path
-      stage_dfwd(sl ^ 1, sdk.x, c + 1);
-      load_dfwd(c + 2);
+      stage_dfwd(dvb, sl ^ 1, sdk.x, c + 1);
+      load_dfwd(dvb, c + 3);
       __syncthreads();
+    };
+    int c = 0;
+#pragma unroll 1
+    for (; c + 1 < nc; c += 2) {
+      chunk(c, dv[1]);
+      chunk(c + 1, dv[0]);
     }
+    if (c < nc) chunk(c, dv[1]);
   } else {
     // prologue: R chunk 0 in the ring, chunks 1 .. 3 in flight
     // Every issue is unconditional (chunks past the end read clamped addresses and
@@ -1323,7 +1334,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
         float2* fw = a.F + (long long)rb * rowstride + ((long long)blk * a.nf + k) * CB + lr;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (rb + e < a.nr) store_g(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
+          if (rb + e < a.nr) store_g_stream(a, (fw - a.F) + e * rowstride, make_float2(re[e], im[e]));
       }
     }
   }
