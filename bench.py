@@ -540,6 +540,77 @@ CALIBRATION_VARIANTS = {0: "the update kernel's grid and 8-byte per-lane accesse
                         2: "flat streams over the arrays (two launches)"}
 
 
+def best_launch_ms(call, reps=5, launches=4):
+    """Best over `reps` runs of the milliseconds per launch of `launches` back-to-back calls,
+    after two untimed calls."""
+    import torch
+    for _ in range(2):
+        call()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / launches
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def spectra_stream_floor(wl, dev):
+    """Milliseconds per launch of the model spectra [nr][nvb][nf][16] complex read and
+    written in place as one flat stream (mdd_calibrate_update, variant 3): the bytes the
+    per-frequency products read as R_k and write as G, with no arithmetic."""
+    import ctypes
+
+    import torch
+
+    from paper_2202_04486_amd import native
+    lib = native.load()
+    nvb = -(-wl.nvs // 16)
+    S = torch.zeros((wl.nr, nvb, wl.nf, 16, 2), dtype=torch.float32, device=dev)
+    one = torch.zeros(4, dtype=torch.float32, device=dev)   # the state arrays are not touched
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (one, one, one, S)]
+
+    def call():
+        native.check("mdd_calibrate_update",
+                     lib.mdd_calibrate_update(*ptrs, wl.nr, wl.nvs, wl.nt, wl.nf, 3, st))
+    ms = best_launch_ms(call)
+    del S
+    torch.cuda.empty_cache()
+    return ms, 2 * 8.0 * wl.nr * nvb * 16 * wl.nf
+
+
+def kernel_rows_floor(wl, dev, idx):
+    """Milliseconds per launch of mdd_calibrate_rows: the batch's kernel rows (rows idx of
+    D_k at every frequency, synthetic values) read with the one-virtual-source products'
+    grid and none of their arithmetic, reductions or barriers."""
+    import ctypes
+
+    import torch
+
+    from paper_2202_04486_amd import native
+    lib = native.load()
+    nrp = -(-wl.nr // 16) * 16
+    nb = int(idx.numel())
+    D = torch.zeros((wl.nf, wl.ns, nrp, 2), dtype=torch.float32, device=dev)
+    out = torch.zeros((wl.nf, -(-nb // 8), nrp // 2, 4), dtype=torch.float32, device=dev)
+    ix = idx.to(device=dev, dtype=torch.int32).contiguous()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        native.check("mdd_calibrate_rows",
+                     lib.mdd_calibrate_rows(ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(ix.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), nb, wl.nf, wl.ns, wl.nr, 0, st))
+    ms = best_launch_ms(call)
+    del D, out
+    torch.cuda.empty_cache()
+    return ms, 8.0 * nb * nrp * wl.nf
+
+
 def update_traffic_floor(wl, dev, reps=5, launches=4):
     """Milliseconds per launch of each variant of mdd_calibrate_update at this workload's
     model size: the Adam update's HBM bytes (model and both moments in place, the
@@ -562,19 +633,7 @@ def update_traffic_floor(wl, dev, reps=5, launches=4):
         def call():
             native.check("mdd_calibrate_update",
                          lib.mdd_calibrate_update(*ptrs, wl.nr, wl.nvs, wl.nt, wl.nf, var, st))
-        for _ in range(2):
-            call()
-        best = None
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(launches):
-                call()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / launches
-            best = ms if best is None else min(best, ms)
-        out[var] = best
+        out[var] = best_launch_ms(call, reps, launches)
     del R, M, V, S
     torch.cuda.empty_cache()
     return out
@@ -852,6 +911,23 @@ def main():
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
     if roofline["bound"] == "hbm":
         add_practical(roofline, practical_hbm_gbs(dev), roof_ms)
+    if dominant == "gemm" and vs1:
+        # The floor of the products' access pattern: the batch's kernel rows read with the
+        # same grid and no arithmetic (mdd_calibrate_rows).
+        log("timing the kernel-row stream of the matrix-vector products")
+        rows_ms, rows_bytes = kernel_rows_floor(wl, dev, idx_tab[0, :lens[0]])
+        roofline["elementwise_peak"] = roofline.pop("practical_peak")
+        roofline.pop("frac_of_practical", None)
+        roofline.pop("traffic_frac_of_practical", None)
+        roofline["practical_peak"] = {
+            "value": rows_bytes / (rows_ms * 1e-3) / 1e9, "unit": "GB/s",
+            "how": "mdd_calibrate_rows: the batch's kernel rows (D_b at every frequency) read "
+                   "with the matrix-vector kernel's grid and none of its arithmetic, reductions "
+                   "or barriers, one partial per group written; the kernel's time includes the "
+                   "launch that adds the group partials",
+            "floor_ms": rows_ms, "bytes_per_launch": rows_bytes}
+        roofline["frac_of_practical"] = rows_ms / roof_ms
+        roofline["frac_ceiling_at_practical"] = gemv_bytes / (rows_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     if dominant == "update" and wl.optimizer == "adam" and not vs1:
         # The floor of the update kernel's own traffic: its bytes moved by a kernel with
         # the same accesses and no arithmetic (mdd_calibrate_update), best of three layouts.
@@ -875,6 +951,21 @@ def main():
         roofline["frac_of_practical"] = floor[best] / roof_ms
         roofline["frac_ceiling_at_practical"] = upd_bytes / (floor[best] * 1e-3) / 1e9 / HBM_PEAK_GBS
 
+    products_floor = None
+    if not vs1:
+        # The products move R_k in, G out, D_b and U_b: the spectra part streamed flat with
+        # no arithmetic, scaled to all of the products' bytes, is the floor of their traffic.
+        log("timing the spectra stream")
+        st_ms, st_bytes = spectra_stream_floor(wl, dev)
+        nvb = -(-wl.nvs // 16)
+        pr_bytes = st_bytes + 8.0 * nb * wl.nr * wl.nf + 8.0 * nb * nvb * 16 * wl.nf
+        products_floor = {"spectra_stream_ms": st_ms, "spectra_bytes": st_bytes,
+                          "spectra_gbs": st_bytes / (st_ms * 1e-3) / 1e9,
+                          "products_bytes": pr_bytes, "floor_ms": st_ms * pr_bytes / st_bytes,
+                          "how": "mdd_calibrate_update variant 3: the model spectra read and "
+                                 "written in place as one flat stream; floor_ms scales it to "
+                                 "the products' bytes (R_k in, G out, D_b and U_b in)"}
+
     def gemm_roof(form):
         ms = per_launch(res[form]["prof"], "gemm")
         if vs1:
@@ -891,7 +982,11 @@ def main():
         hw = gemm_flops * (3 if split else 1 if form == "fp32_cgemm" else
                            fp32_mfma_share(nb, wl.nr))                 # what the MFMA units execute
         tr = stored_traffic(args.workload, f"gemm_{form}")
-        return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12,
+        hbm = {}
+        if products_floor:
+            hbm = {"hbm_bytes_frac": products_floor["products_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "frac_of_traffic_floor": products_floor["floor_ms"] / ms}
+        return {"ms": ms, "useful_tflops": gemm_flops / (ms * 1e-3) / 1e12, **hbm,
                 "counted_tflops": counted / (ms * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS[form],
                 "frac": counted / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[form],
                 "mfma_tflops": hw / (ms * 1e-3) / 1e12,
@@ -916,6 +1011,7 @@ def main():
         "roofline": roofline,
         "method_roofline_frac": (alg_bytes / HBM_PEAK_GBS / 1e9) / (ms_step * 1e-3),
         "gemm_roofline": {f: gemm_roof(f) for f in forms},
+        "products_traffic_floor": products_floor,
         "step_ms_quantiles": {q: float(np.percentile(fp["per_step"], v))
                               for q, v in (("p10", 10), ("median", 50), ("p90", 90))},
         "step_ms_quantiles_source": "one HIP event pair per step over K further steps",

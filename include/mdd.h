@@ -315,13 +315,29 @@ mdd_status mdd_profile_read(mdd_plan* plan, double* ms_host, int64_t* count_host
  * system sets for the update kernel at these sizes.  variant 0: the update kernel's
  * grid, workgroup mapping, spectra staging and 8-byte per-lane accesses; 1: the same
  * with 16-byte per-lane accesses; 2: flat streams over the three arrays and the
- * spectra (two launches).  The arrays' contents are overwritten with meaningless
+ * spectra (two launches); 3: the spectra alone as a flat stream (the bytes the
+ * per-frequency products read and write besides D_b and U_b).  The arrays' contents
+ * are overwritten with meaningless
  * values.  Pointers 16-byte aligned; enqueued on `stream`.  Errors: EINVAL (NULL,
  * misaligned, variant), ESHAPE (rows or ncols outside [1, 4096], nt not one of
  * 128, 256, 512, 1024, nf outside [1, nt/2 + 1]), EHIP. */
 mdd_status mdd_calibrate_update(float* R, float* s0, float* s1, float* spec, int32_t rows,
                                 int32_t ncols, int32_t nt, int32_t nf, int32_t variant,
                                 void* stream);
+
+/* Measurement aid, not a step of the method: reads the batch's kernel rows, row idx[b]
+ * of D_k for every frequency k and batch entry b (D [nf][ns][round16(nr)] complex
+ * float32, idx nb int32 on the device; an index outside [0, ns) reads row 0), with the
+ * grid of the one-virtual-source products (nf x groups workgroups, batch entries split
+ * into groups of ceil(nb / groups)) but none of their arithmetic, reductions or
+ * barriers, and writes one partial per (frequency, group, receiver pair) to out
+ * (nf * groups * round16(nr) / 2 float4).  Its duration is the floor of that access
+ * pattern.  groups 0 takes the number the products kernel uses for (nb, nf).  Pointers
+ * D and out 16-byte aligned; enqueued on `stream`.  Errors: EINVAL (NULL, misaligned),
+ * ESHAPE (nb outside [1, 64], ns outside [1, 2^20], nr outside [1, 4096], nf outside
+ * [1, 2049], groups outside [1, nb]), EHIP. */
+mdd_status mdd_calibrate_rows(const float* D, const int32_t* idx, float* out, int32_t nb,
+                              int32_t nf, int32_t ns, int32_t nr, int32_t groups, void* stream);
 
 /* Static description of a status code. */
 const char* mdd_status_string(mdd_status status);

@@ -714,12 +714,28 @@ mdd_status mdd_calibrate_update(float* R, float* s0, float* s1, float* spec, int
   if ((reinterpret_cast<uintptr_t>(R) | reinterpret_cast<uintptr_t>(s0) |
        reinterpret_cast<uintptr_t>(s1) | reinterpret_cast<uintptr_t>(spec)) & 15)
     return MDD_EINVAL;
-  if (variant < 0 || variant > 2) return MDD_EINVAL;
+  if (variant < 0 || variant > 3) return MDD_EINVAL;
   if (rows < 1 || rows > MAX_EXTENT || ncols < 1 || ncols > MAX_EXTENT || !valid_nt(nt))
     return MDD_ESHAPE;
   if (nf < 1 || nf > nt / 2 + 1) return MDD_ESHAPE;
   return launch_calibrate_update(R, s0, s1, reinterpret_cast<float2*>(spec), rows, ncols, nt, nf,
                                  variant, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? MDD_OK
+             : MDD_EHIP;
+}
+
+mdd_status mdd_calibrate_rows(const float* D, const int32_t* idx, float* out, int32_t nb,
+                              int32_t nf, int32_t ns, int32_t nr, int32_t groups, void* stream) {
+  if (!D || !idx || !out) return MDD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(out)) & 15) return MDD_EINVAL;
+  if (nb < 1 || nb > NB_LIMIT || ns < 1 || ns > MAX_STREAM_NS || nr < 1 || nr > MAX_EXTENT ||
+      nf < 1 || nf > MAX_EXTENT / 2 + 1)
+    return MDD_ESHAPE;
+  if (groups == 0) groups = gemv_groups(nb, nf);
+  if (groups < 1 || groups > nb) return MDD_ESHAPE;
+  return launch_calibrate_rows(reinterpret_cast<const float2*>(D), idx, reinterpret_cast<float2*>(out),
+                               nb, nf, ns, static_cast<int>(round16(nr)), groups,
+                               reinterpret_cast<hipStream_t>(stream)) == hipSuccess
              ? MDD_OK
              : MDD_EHIP;
 }

@@ -10,6 +10,13 @@
 // kernel's time on this device, set by the memory system alone.  Two other layouts
 // of the same bytes are measured beside it: 16 bytes per lane, and flat streams over
 // whole arrays (the fastest form a plain elementwise kernel takes here).
+//
+// The products for one virtual source are bound by one pass over the batch's kernel
+// rows.  k_cal_rows reads exactly those rows (the rows idx[b] of every frequency) with
+// the grid of the matrix-vector kernel (nf x groups workgroups, a frequency's groups on
+// one XCD, a thread's receiver pairs tid + 256 m), but with no reduction, residual or
+// barrier between rows, and writes the same group partials; its time is the floor of
+// that access pattern.
 #include "device_common.h"
 #include "mdd_internal.h"
 
@@ -180,6 +187,44 @@ __global__ __launch_bounds__(256) void k_cal_flat_spec(float* S, long long n4) {
   }
 }
 
+// Rows idx[b] of D_k for the batch entries of group p of frequency k (group size
+// ceil(nb / groups)), each thread summing its receiver pairs over the rows, four rows
+// in flight; then one partial per (k, p, pair).
+template <int MQ>
+__global__ __launch_bounds__(256) void k_cal_rows(const float4* __restrict__ D, const int* idx,
+                                                  float4* out, int nb, int nf, int ns, int npair,
+                                                  int groups) {
+  const int total = nf * groups, bid = blockIdx.x, full = (total / 8) * 8;
+  const int logical = bid < full ? (bid % 8) * (total / 8) + bid / 8 : bid;
+  const int k = logical / groups, p = logical % groups;
+  const int rpg = (nb + groups - 1) / groups;
+  const int i0 = p * rpg, i1 = min(nb, i0 + rpg);
+  const int tid = threadIdx.x;
+  cal4 acc[MQ];
+#pragma unroll
+  for (int m = 0; m < MQ; ++m) acc[m] = cal4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
+    int sidx = idx[i];
+    if (sidx < 0 || sidx >= ns) sidx = 0;
+    const float4* row = D + ((long long)k * ns + sidx) * npair;
+#pragma unroll
+    for (int m = 0; m < MQ; ++m) {
+      const int q = tid + 256 * m;
+      const float4 v = row[q < npair ? q : npair - 1];
+      acc[m] += cal4{v.x, v.y, v.z, v.w};
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MQ; ++m) {
+    const int q = tid + 256 * m;
+    if (q < npair) {
+      const cal4 v = acc[m];
+      out[((long long)k * groups + p) * npair + q] = make_float4(v.x, v.y, v.z, v.w);
+    }
+  }
+}
+
 template <int NT, int W>
 hipError_t launch_cal(const CalArgs& a, hipStream_t s) {
   using C = CalCfg<NT>;
@@ -202,6 +247,12 @@ hipError_t launch_cal_nt(int variant, const CalArgs& a, hipStream_t s) {
 hipError_t launch_calibrate_update(float* R, float* M, float* V, float2* spec, int rows,
                                    int ncols, int nt, int nf, int variant, hipStream_t s) {
   CalArgs a{R, M, V, spec, rows, ncols, nblocks(ncols), nf};
+  if (variant == 3) {  // the spectra alone, as a flat stream
+    const long long n4 = (long long)rows * a.ncb * nf * CB / 2;
+    hipLaunchKernelGGL(k_cal_flat_spec, dim3((unsigned)((n4 + 511) / 512)), dim3(256), 0, s,
+                       reinterpret_cast<float*>(spec), n4);
+    return hipGetLastError();
+  }
   if (variant == 2) {
     const long long n2 = (long long)rows * ncols * nt / 2;
     const long long n4 = (long long)rows * a.ncb * nf * CB / 2;
@@ -220,6 +271,20 @@ hipError_t launch_calibrate_update(float* R, float* M, float* V, float2* spec, i
     case 1024: return launch_cal_nt<1024>(variant, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_calibrate_rows(const float2* D, const int32_t* idx, float2* out, int nb, int nf,
+                                 int ns, int nrp, int groups, hipStream_t s) {
+  const int npair = nrp / 2;
+  const dim3 grid(nf * groups), block(256);
+  const float4* D4 = reinterpret_cast<const float4*>(D);
+  float4* o4 = reinterpret_cast<float4*>(out);
+  if (npair <= 256) hipLaunchKernelGGL(k_cal_rows<1>, grid, block, 0, s, D4, idx, o4, nb, nf, ns, npair, groups);
+  else if (npair <= 512) hipLaunchKernelGGL(k_cal_rows<2>, grid, block, 0, s, D4, idx, o4, nb, nf, ns, npair, groups);
+  else if (npair <= 1024) hipLaunchKernelGGL(k_cal_rows<4>, grid, block, 0, s, D4, idx, o4, nb, nf, ns, npair, groups);
+  else if (npair <= 2048) hipLaunchKernelGGL(k_cal_rows<8>, grid, block, 0, s, D4, idx, o4, nb, nf, ns, npair, groups);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace mdd

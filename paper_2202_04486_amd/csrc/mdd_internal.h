@@ -124,6 +124,10 @@ hipError_t launch_sigma(const float2* Df, int nf, int ns, int nr, int nrp, int i
 // Measurement aid (calibrate.hip): the update kernel's HBM traffic without its transforms.
 hipError_t launch_calibrate_update(float* R, float* M, float* V, float2* spec, int rows,
                                    int ncols, int nt, int nf, int variant, hipStream_t s);
+// Measurement aid (calibrate.hip): the batch's kernel rows [nf][ns][nrp] read with the
+// matrix-vector kernel's grid and no arithmetic; out holds nf * groups * nrp / 2 float4.
+hipError_t launch_calibrate_rows(const float2* D, const int32_t* idx, float2* out, int nb, int nf,
+                                 int ns, int nrp, int groups, hipStream_t s);
 
 // The library's static workspace (noalloc.hip): its size, and its address on `device`,
 // which must be the current device (looked up once per device, then cached).

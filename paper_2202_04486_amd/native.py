@@ -29,7 +29,7 @@ EXPORTS = ("mdd_workspace_bytes", "mdd_plan_create", "mdd_plan_destroy", "mdd_pl
            "mdd_stoch_grad", "mdd_stoch_grad_noalloc", "mdd_step", "mdd_full_grad", "mdd_full_step",
            "mdd_reciprocity", "mdd_check_batch_host", "mdd_invalidate_model_spectra",
            "mdd_sigma_max2",
-           "mdd_profile_enable", "mdd_profile_read", "mdd_calibrate_update",
+           "mdd_profile_enable", "mdd_profile_read", "mdd_calibrate_update", "mdd_calibrate_rows",
            "mdd_status_string", "mdd_plan_last_hip_error")
 
 
@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
         "mdd_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]),
         "mdd_calibrate_update": (_I32, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P]),
+        "mdd_calibrate_rows": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P]),
         "mdd_status_string": (ctypes.c_char_p, [_I32]),
         "mdd_plan_last_hip_error": (_I32, [_P]),
     }

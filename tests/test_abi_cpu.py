@@ -181,11 +181,31 @@ def test_calibration_rejects_bad_arguments_on_the_host(lib):
     E, S = native.MDD_EINVAL, native.MDD_ESHAPE
     assert lib.mdd_calibrate_update(None, p, p, p, 4, 20, 512, 200, 0, None) == E
     assert lib.mdd_calibrate_update(p, p, p, ctypes.c_void_p(4104), 4, 20, 512, 200, 0, None) == E
-    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 200, 3, None) == E
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 200, 4, None) == E
+    assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 200, -1, None) == E
     assert lib.mdd_calibrate_update(p, p, p, p, 0, 20, 512, 200, 0, None) == S
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 5000, 512, 200, 0, None) == S
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 500, 200, 0, None) == S
     assert lib.mdd_calibrate_update(p, p, p, p, 4, 20, 512, 258, 0, None) == S
+
+
+def test_row_calibration_rejects_bad_arguments_on_the_host(lib):
+    """mdd_calibrate_rows (the kernel-row stream of the one-virtual-source products)
+    checks pointers, alignment and every extent before any HIP call."""
+    p = ctypes.c_void_p(4096)
+    E, S = native.MDD_EINVAL, native.MDD_ESHAPE
+    assert lib.mdd_calibrate_rows(None, p, p, 64, 200, 1600, 1600, 0, None) == E
+    assert lib.mdd_calibrate_rows(p, None, p, 64, 200, 1600, 1600, 0, None) == E
+    assert lib.mdd_calibrate_rows(p, p, None, 64, 200, 1600, 1600, 0, None) == E
+    assert lib.mdd_calibrate_rows(ctypes.c_void_p(4104), p, p, 64, 200, 1600, 1600, 0, None) == E
+    assert lib.mdd_calibrate_rows(p, p, ctypes.c_void_p(4100), 64, 200, 1600, 1600, 0, None) == E
+    assert lib.mdd_calibrate_rows(p, p, p, 0, 200, 1600, 1600, 0, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 65, 200, 1600, 1600, 0, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 64, 0, 1600, 1600, 0, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 64, 200, 0, 1600, 0, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 64, 200, 1600, 4097, 0, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 64, 200, 1600, 1600, 65, None) == S
+    assert lib.mdd_calibrate_rows(p, p, p, 64, 200, 1600, 1600, -1, None) == S
 
 
 def test_noalloc_gradient_rejects_on_the_host(lib):
