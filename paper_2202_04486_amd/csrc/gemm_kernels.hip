@@ -892,6 +892,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int KSW = PIPE_KC / 4 / 4;        // k-steps per wave (4 waves split K)
   constexpr int PAIRS = PIPE_KC / 2;          // float4 pairs per D row
   constexpr int DPT = MB * PAIRS / 256;       // D float4 per thread
+  static_assert(KSW == 14, "the wait for the next item's operands names each of them");
   __shared__ float2 s_d[MB * DST];
   __shared__ float2 s_part[4 * MB * NW];
   __shared__ float2 s_res[MB * RST];
@@ -940,17 +941,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       return a.Uf[urow_off(a, k, urow, s_idx[urow]) + vs];
     return make_float2(0.f, 0.f);
   };
-  auto stage_d = [&](int k) {   // D_{b,k} rows -> LDS
+  // D_{b,k} rows -> LDS.  The loads are unconditional (a rejected row reads row 0, a
+  // pair past the row reads its last pair) and all in flight at once; what they should
+  // not have read is zeroed when it is written to LDS.
+  auto stage_d = [&](int k) {
+    float4 v[DPT];
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int i = tid + 256 * q;
       const int b = i / PAIRS, rr = 2 * (i % PAIRS);
       const long long off = s_drow[b];
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (off >= 0 && rr < a.nr)
-        v = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.dns * a.nrp + off + rr);
-      s_d[b * DST + rr] = make_float2(v.x, v.y);
-      s_d[b * DST + rr + 1] = make_float2(v.z, v.w);
+      v[q] = *reinterpret_cast<const float4*>(a.Df + (size_t)k * a.dns * a.nrp + (off >= 0 ? off : 0) +
+                                              min(rr, a.nrp - 2));
+    }
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int i = tid + 256 * q;
+      const int b = i / PAIRS, rr = 2 * (i % PAIRS);
+      if (!(s_drow[b] >= 0 && rr < a.nr)) v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s_d[b * DST + rr] = make_float2(v[q].x, v[q].y);
+      s_d[b * DST + rr + 1] = make_float2(v[q].z, v[q].w);
     }
   };
 
@@ -958,6 +968,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   int cur = start;
   int k = cur / nvb, cg = cur % nvb;
   float2 bfr[KSW], bnx[KSW];
+#pragma unroll
+  for (int q = 0; q < KSW; ++q) bnx[q] = make_float2(0.f, 0.f);
   load_b(bfr, k, cg);
   float2 up = load_u(k, cg);
   stage_d(k);
@@ -1014,6 +1026,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     lsum += lpart;
     if (tid == 0) a.loss_part[cur] = 0.0;
     __syncthreads();    // publishes s_res
+    // The next item's operands are waited for here, before this item's G stores are
+    // issued: loads and stores retire in order under one counter, so a wait at the top
+    // of the next iteration would wait for every store of this one as well.
+    asm volatile("" ::"v"(bnx[0].x), "v"(bnx[1].x), "v"(bnx[2].x), "v"(bnx[3].x), "v"(bnx[4].x),
+                 "v"(bnx[5].x), "v"(bnx[6].x), "v"(bnx[7].x), "v"(bnx[8].x), "v"(bnx[9].x),
+                 "v"(bnx[10].x), "v"(bnx[11].x), "v"(bnx[12].x), "v"(bnx[13].x), "v"(upn.x));
 
     // adjoint: G_k = D_b^H Res over this wave's receiver tiles, written over R_k
     for (int mt = wave; mt * 16 < a.nr; mt += 4) {

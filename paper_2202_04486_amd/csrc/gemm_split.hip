@@ -138,8 +138,11 @@ struct SCfg {
   static constexpr int MT_STEP = 4 / TNB;    // row-tile stride between a wave's tiles
   static constexpr int KCMAX = 64;         // receiver chunk
   static constexpr int KSW = KCMAX / 32;     // forward k-steps per chunk
-  static constexpr int RP = KCMAX + 8;       // forward D plane row pitch (elements)
-  static constexpr int BP = MB + 8;          // adjoint D / residual plane row pitch
+  // Plane row pitches: 16 elements (32 bytes) of padding make the rows of one MFMA
+  // operand read (16 rows, 16-byte pieces four lanes apart) fall in disjoint LDS banks;
+  // with 8 elements of padding half of the read cycles were bank conflicts.
+  static constexpr int RP = KCMAX + 16;      // forward D plane row pitch (elements)
+  static constexpr int BP = MB + 16;         // adjoint D / residual plane row pitch
   static constexpr int DF = 4 * MB * RP;     // elements
   static constexpr int DA = 4 * KCMAX * BP;
   static constexpr int DSZ = DF > DA ? DF : DA;
