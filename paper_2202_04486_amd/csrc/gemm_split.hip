@@ -920,13 +920,23 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_split_ws(GemmArgs a) {
     const int slot = c & 1;
     if constexpr (SPLIT_RING) {
       float x[4][8];  // column lcp re, im; column lcp + 1 re, im; rows lrg .. lrg + 7
+      if (lblk_ok && c * KC + lrg + LPT <= a.nr) {  // every row real: no selects
 #pragma unroll
-      for (int q = 0; q < LPT; ++q) {
-        const bool ok = lblk_ok && c * KC + lrg + q < a.nr;
-        x[0][q] = ok ? src[q].x : 0.f;
-        x[1][q] = ok ? src[q].y : 0.f;
-        x[2][q] = ok ? src[q].z : 0.f;
-        x[3][q] = ok ? src[q].w : 0.f;
+        for (int q = 0; q < LPT; ++q) {
+          x[0][q] = src[q].x;
+          x[1][q] = src[q].y;
+          x[2][q] = src[q].z;
+          x[3][q] = src[q].w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+          const bool ok = lblk_ok && c * KC + lrg + q < a.nr;
+          x[0][q] = ok ? src[q].x : 0.f;
+          x[1][q] = ok ? src[q].y : 0.f;
+          x[2][q] = ok ? src[q].z : 0.f;
+          x[3][q] = ok ? src[q].w : 0.f;
+        }
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {  // the two columns
