@@ -241,9 +241,9 @@ __device__ __forceinline__ double tile_sum(double v, double* red) {
 }
 
 // One workgroup per tile of CB traces, one wavefront per trace (or several
-// traces per wavefront for short traces).  Update modes load a trace's model
-// and optimiser state right after its inverse transform and store them right
-// after the update, so that each element's read and write are close in time.
+// traces per wavefront for short traces).  Update modes request a trace's model
+// and optimiser state just before its inverse transform (the loads are in flight
+// while it runs) and store them right after the update.
 template <int NT, int MODE>
 __global__ __launch_bounds__((TraceCfg<NT, MODE>::THREADS)) void k_trace(TraceArgs a) {
   using C = TraceCfg<NT, MODE>;
@@ -349,9 +349,9 @@ __global__ __launch_bounds__((TraceCfg<NT, MODE>::THREADS)) void k_trace(TraceAr
         if (j == 0 && nf <= N2) part += (double)xn.x * xn.x;
       }
     } else {
+      load_state(it);  // in flight during the inverse transform
       irfft_merge<NT, SPS>(v, j, s_spec, c, nf, s_tw);
       fft_half<NT, true>(v, j, sc, s_tw);
-      load_state(it);  // read just before its update, written back soon after
       const float inv_n2 = 1.0f / float(N2);
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[r] = cscale(v[r], inv_n2);  // time samples 2n, 2n+1
