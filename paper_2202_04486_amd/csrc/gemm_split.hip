@@ -779,10 +779,11 @@ __global__ __launch_bounds__(256) void k_gemm_spipe(GemmArgs a) {
 // kernel (each owns one 16-column tile and two of the four row tiles).  Four
 // loader waves only stream R_k: they keep WS_DEPTH 64-receiver chunks in flight
 // in their registers and hand each to the compute waves through a two-slot LDS
-// ring of float32 values.  D_{b,k} chunks are double-buffered as well, so a
-// single barrier separates consecutive chunks.  (With one role per wave, each
-// wave has one chunk in flight and waits on memory for about half of its time.)
-// In the barrier-free adjoint all twelve waves take receiver tiles.
+// ring (bf16: already split into hi / lo planes; fp16: float32 values).  D_{b,k}
+// chunks are double-buffered as well, so a single barrier separates consecutive
+// chunks.  (With one role per wave, each wave has one chunk in flight and waits on
+// memory for about half of its time.)  In the barrier-free adjoint all twelve waves
+// take receiver tiles.
 constexpr int WS_DEPTH = 3;
 constexpr int WS_CW = 8;                   // compute waves (two per SIMD)
 constexpr int WS_LW = 4;                   // loader waves
